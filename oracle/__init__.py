@@ -1,0 +1,338 @@
+"""CPU oracle for the importance-sampled first-passage simulation.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, by the smoke check and by the
+CPU-baseline leg of bench.py; never by the product package, which shares no
+code with it.
+
+Two parts:
+  * ``simulate`` -- the per-trajectory Euler-Maruyama loop with the importance
+    weight, in C (``fpt_oracle.c``), in a binary32 mirror mode (the step count
+    is decided in the kernel's precision) and a binary64 reference mode;
+  * ``histogram`` -- the per-bin estimators written out from their plain
+    definitions in numpy, binary64: counts and weight sums per bin
+    (Sec. 2.1 eq. eq_bin_pdf_reconstrcuted and Sec. 2.2
+    eq. eq_bin_pdf_reconstrcuted_weighted_naive), jackknife subsets
+    (Sec. 2.1), moments of ln w per bin (Sec. 2.4), and the Kish effective
+    sample size of each bin.
+
+``refmath`` holds the binary64 closed forms and quadratures that pin the
+simulation (mean and variance of N, Sturm-Liouville tail, Brownian first
+passage, lattice Gaussian).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(HERE, "_liboracle.so")
+
+POT_QUADRATIC, POT_QUADRATIC_BUMP, POT_FLAT = 0, 1, 2
+BIAS_NONE, BIAS_NOISE_SCALED, BIAS_POWER = 0, 1, 2
+ST_ENDED, ST_CENSORED, ST_ESCAPED = 1, 2, 3
+MODE_F32, MODE_F64 = 0, 1
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [
+        ("pot_kind", ctypes.c_int),
+        ("m", ctypes.c_double), ("a", ctypes.c_double), ("phi0", ctypes.c_double),
+        ("w", ctypes.c_double), ("V0", ctypes.c_double),
+        ("bias_kind", ctypes.c_int),
+        ("A", ctypes.c_double),
+        ("p", ctypes.c_int),
+        ("phi_in", ctypes.c_double), ("phi_end", ctypes.c_double),
+        ("phi_uv", ctypes.c_double), ("phi_esc", ctypes.c_double), ("dN", ctypes.c_double),
+        ("k_max", ctypes.c_uint64),
+        ("seed", ctypes.c_uint64),
+        ("stream", ctypes.c_uint32),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load (building first if needed) the C oracle."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            from . import build as _b
+            _b.build()
+        L = ctypes.CDLL(_LIB_PATH)
+        u32p = ctypes.POINTER(ctypes.c_uint32)
+        f32p = ctypes.POINTER(ctypes.c_float)
+        f64p = ctypes.POINTER(ctypes.c_double)
+        u64p = ctypes.POINTER(ctypes.c_uint64)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        L.oracle_philox4x32_10.argtypes = [u32p, u32p, u32p]
+        L.oracle_uniform24.argtypes = [ctypes.c_uint32]
+        L.oracle_uniform24.restype = ctypes.c_float
+        L.oracle_log_f32.argtypes = [ctypes.c_float]
+        L.oracle_log_f32.restype = ctypes.c_float
+        L.oracle_exp_f32.argtypes = [ctypes.c_float]
+        L.oracle_exp_f32.restype = ctypes.c_float
+        L.oracle_log_f32_batch.argtypes = [f32p, f32p, ctypes.c_int64]
+        L.oracle_exp_f32_batch.argtypes = [f32p, f32p, ctypes.c_int64]
+        L.oracle_sincos2pi_f32_batch.argtypes = [f32p, f32p, f32p, ctypes.c_int64]
+        L.oracle_normals_f32_batch.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                                               ctypes.c_uint32, ctypes.c_uint32, f32p]
+        L.oracle_normals_f64_batch.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                                               ctypes.c_uint32, ctypes.c_uint32, f64p]
+        L.oracle_drift_noise_bias_f32.argtypes = [ctypes.POINTER(_Params), ctypes.c_float, f32p]
+        L.oracle_simulate.argtypes = [ctypes.POINTER(_Params), ctypes.c_uint64, ctypes.c_uint64,
+                                      ctypes.c_uint64, ctypes.c_int, u64p, f64p, f64p, i32p,
+                                      ctypes.c_int]
+        L.oracle_simulate.restype = ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a, ct):
+    return a.ctypes.data_as(ctypes.POINTER(ct))
+
+
+# --------------------------------------------------------------------------
+# Model description (the paper's inputs: V, V', phi_in, phi_end, bias
+# amplitude and shape, phi_UV, number of runs; Sec. 2.3 and Sec. 3).
+# --------------------------------------------------------------------------
+@dataclass
+class Model:
+    pot: int = POT_QUADRATIC
+    m: float = 1.0
+    a: float = 0.0
+    phi0: float = 0.0
+    w: float = 1.0
+    V0: float = 1.0
+    bias: int = BIAS_NONE
+    A: float = 0.0
+    p: int = 1
+    phi_in: float = 5.0
+    phi_end: float = float(np.sqrt(2.0))
+    phi_uv: float = float("inf")
+    phi_esc: float = 0.0          # 0 -> 100 phi_in without a wall (the paper's "infinite" wall)
+    dN: float = 1e-3
+    k_max: int = 1 << 20
+    stream: int = 0
+
+    def esc(self) -> float:
+        if np.isfinite(self.phi_uv):
+            return float("inf")
+        return self.phi_esc if self.phi_esc > 0 else 100.0 * self.phi_in
+
+    def to_c(self, seed: int) -> _Params:
+        return _Params(self.pot, self.m, self.a, self.phi0, self.w, self.V0, self.bias, self.A,
+                       self.p, self.phi_in, self.phi_end, self.phi_uv, self.esc(), self.dN,
+                       int(self.k_max), int(seed), int(self.stream))
+
+
+@dataclass
+class Trajectories:
+    t: np.ndarray       # uint64 trajectory ids
+    k: np.ndarray       # uint64 step counts
+    lw: np.ndarray      # float64 ln w
+    phi: np.ndarray     # float64 final field value
+    status: np.ndarray  # int32: 1 ended, 2 censored, 3 escaped
+    threads: int = 1
+
+
+def simulate(model: Model, seed: int, n: int, t0: int = 0, stride: int = 1,
+             mode: int = MODE_F32, threads: int = 0) -> Trajectories:
+    """Run trajectories t = t0 + i*stride, i < n, one by one."""
+    L = lib()
+    n = int(n)
+    k = np.zeros(n, np.uint64)
+    lw = np.zeros(n, np.float64)
+    phi = np.zeros(n, np.float64)
+    st = np.zeros(n, np.int32)
+    P = model.to_c(seed)
+    used = L.oracle_simulate(ctypes.byref(P), t0, stride, n, mode, _ptr(k, ctypes.c_uint64),
+                             _ptr(lw, ctypes.c_double), _ptr(phi, ctypes.c_double),
+                             _ptr(st, ctypes.c_int32), int(threads))
+    t = (np.uint64(t0) + np.arange(n, dtype=np.uint64) * np.uint64(stride)).astype(np.uint64)
+    return Trajectories(t, k, lw, phi, st, used)
+
+
+def philox(ctr, key):
+    L = lib()
+    c = np.asarray(ctr, np.uint32).copy()
+    kk = np.asarray(key, np.uint32).copy()
+    o = np.zeros(4, np.uint32)
+    L.oracle_philox4x32_10(_ptr(c, ctypes.c_uint32), _ptr(kk, ctypes.c_uint32), _ptr(o, ctypes.c_uint32))
+    return o
+
+
+def normals_f32(seed: int, stream: int, t: int, j0: int, nj: int) -> np.ndarray:
+    out = np.zeros(4 * nj, np.float32)
+    lib().oracle_normals_f32_batch(seed, stream, t, j0, nj, _ptr(out, ctypes.c_float))
+    return out
+
+
+def normals_f64(seed: int, stream: int, t: int, j0: int, nj: int) -> np.ndarray:
+    out = np.zeros(4 * nj, np.float64)
+    lib().oracle_normals_f64_batch(seed, stream, t, j0, nj, _ptr(out, ctypes.c_double))
+    return out
+
+
+def log_f32(x: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(x, np.float32)
+    y = np.empty_like(x)
+    lib().oracle_log_f32_batch(_ptr(x, ctypes.c_float), _ptr(y, ctypes.c_float), x.size)
+    return y
+
+
+def exp_f32(x: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(x, np.float32)
+    y = np.empty_like(x)
+    lib().oracle_exp_f32_batch(_ptr(x, ctypes.c_float), _ptr(y, ctypes.c_float), x.size)
+    return y
+
+
+def sincos2pi_f32(u: np.ndarray):
+    u = np.ascontiguousarray(u, np.float32)
+    c = np.empty_like(u)
+    s = np.empty_like(u)
+    lib().oracle_sincos2pi_f32_batch(_ptr(u, ctypes.c_float), _ptr(c, ctypes.c_float),
+                                     _ptr(s, ctypes.c_float), u.size)
+    return c, s
+
+
+def drift_noise_bias_f32(model: Model, phi: float):
+    out = np.zeros(3, np.float32)
+    P = model.to_c(0)
+    lib().oracle_drift_noise_bias_f32(ctypes.byref(P), ctypes.c_float(phi), _ptr(out, ctypes.c_float))
+    return out
+
+
+# --------------------------------------------------------------------------
+# Per-bin estimators from their plain definitions (binary64).
+# --------------------------------------------------------------------------
+def _lse(x: np.ndarray) -> float:
+    """log(sum(exp(x))) with the maximum factored out; -inf for no terms."""
+    if x.size == 0:
+        return -np.inf
+    mx = np.max(x)
+    if not np.isfinite(mx):
+        return float(mx)
+    return float(mx + np.log(np.sum(np.exp(x - mx))))
+
+
+@dataclass
+class Histogram:
+    edges: np.ndarray
+    n_traj: int
+    n_sub: int
+    count: np.ndarray       # [B+4] rows: bins, underflow, overflow, censored, escaped
+    lse_w: np.ndarray       # log sum w per row
+    lse_w2: np.ndarray      # log sum w^2 per row
+    jk_count: np.ndarray    # [n_sub, B+4]
+    jk_lse_w: np.ndarray    # [n_sub, B+4]
+    mean_lnw: np.ndarray    # per row (nan if empty)
+    m2_lnw: np.ndarray      # central moments of ln w per row: (1/n) sum (x - mean)^j
+    m3_lnw: np.ndarray
+    m4_lnw: np.ndarray
+    total_steps: int
+    n_completed: int
+    lse_w_all: float
+    lse_w2_all: float
+    lse_wk: float           # log sum w k
+    lse_wk2: float          # log sum w k^2
+    sum_k: float
+    sum_k2: float
+    n_per_sub: np.ndarray   # launched runs per jackknife subset
+
+    # --- estimators ---
+    def widths(self):
+        return np.diff(self.edges)
+
+    def log_p_naive(self):
+        """log P_hat_j = log(sum_i w_i / (Delta_j n_total)), n_total = all launched runs."""
+        B = len(self.edges) - 1
+        return self.lse_w[:B] - np.log(self.widths()) - np.log(self.n_traj)
+
+    def jackknife_rel_err(self):
+        """Relative error of P_hat_j from the spread over subsets, rescaled by 1/sqrt(n_sub)."""
+        B = len(self.edges) - 1
+        ps = np.exp(self.jk_lse_w[:, :B]) / (self.widths()[None, :] * self.n_per_sub[:, None])
+        p = np.exp(self.log_p_naive())
+        sd = np.std(ps, axis=0, ddof=1)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            return sd / np.sqrt(self.n_sub) / p
+
+    def kish_rel_err2(self):
+        """sum w^2 / (sum w)^2 - 1/n_total: the delta-method relative variance of P_hat_j."""
+        B = len(self.edges) - 1
+        with np.errstate(invalid="ignore"):
+            return np.exp(self.lse_w2[:B] - 2 * self.lse_w[:B]) - 1.0 / self.n_traj
+
+    def ess(self):
+        B = len(self.edges) - 1
+        with np.errstate(invalid="ignore"):
+            return np.exp(2 * self.lse_w[:B] - self.lse_w2[:B])
+
+
+def bin_rows(k: np.ndarray, status: np.ndarray, dN: float, edges: np.ndarray) -> np.ndarray:
+    """Row of each run: bin j with e_j < N <= e_{j+1} (N = k dN); B for N <= e_0;
+    B+1 for N > e_B; B+2 censored; B+3 escaped."""
+    B = len(edges) - 1
+    N = k.astype(np.float64) * dN
+    rows = np.searchsorted(edges, N, side="left") - 1   # e_j < N <= e_{j+1}  ->  j
+    rows = np.where(N <= edges[0], B, rows)
+    rows = np.where(N > edges[-1], B + 1, rows)
+    rows = np.where(status == ST_CENSORED, B + 2, rows)
+    rows = np.where(status == ST_ESCAPED, B + 3, rows)
+    return rows.astype(np.int64)
+
+
+def histogram(tr: Trajectories, dN: float, edges, n_sub: int = 16, n_traj: int | None = None) -> Histogram:
+    edges = np.asarray(edges, np.float64)
+    B = len(edges) - 1
+    R = B + 4
+    n_traj = len(tr.k) if n_traj is None else n_traj
+    rows = bin_rows(tr.k, tr.status, dN, edges)
+    sub = (tr.t % np.uint64(n_sub)).astype(np.int64)
+    count = np.zeros(R, np.int64)
+    lse_w = np.full(R, -np.inf)
+    lse_w2 = np.full(R, -np.inf)
+    jk_count = np.zeros((n_sub, R), np.int64)
+    jk_lse_w = np.full((n_sub, R), -np.inf)
+    mean = np.full(R, np.nan)
+    m2 = np.full(R, np.nan)
+    m3 = np.full(R, np.nan)
+    m4 = np.full(R, np.nan)
+    order = np.argsort(rows, kind="stable")
+    rs = rows[order]
+    bounds = np.searchsorted(rs, np.arange(R + 1))
+    for r in range(R):
+        idx = order[bounds[r]:bounds[r + 1]]
+        if idx.size == 0:
+            continue
+        x = tr.lw[idx]
+        count[r] = idx.size
+        lse_w[r] = _lse(x)
+        lse_w2[r] = _lse(2.0 * x)
+        mu = np.mean(x)
+        d = x - mu
+        mean[r] = mu
+        m2[r] = np.mean(d ** 2)
+        m3[r] = np.mean(d ** 3)
+        m4[r] = np.mean(d ** 4)
+        s = sub[idx]
+        for q in range(n_sub):
+            xs = x[s == q]
+            jk_count[q, r] = xs.size
+            jk_lse_w[q, r] = _lse(xs)
+    kf = tr.k.astype(np.float64)
+    with np.errstate(divide="ignore"):
+        lnk = np.log(kf)
+    n_per_sub = np.bincount(sub, minlength=n_sub).astype(np.float64)
+    if n_traj != len(tr.k):
+        # runs not simulated here (e.g. a sub-range) still count as launched
+        n_per_sub = np.full(n_sub, n_traj / n_sub)
+    return Histogram(edges, n_traj, n_sub, count, lse_w, lse_w2, jk_count, jk_lse_w,
+                     mean, m2, m3, m4, int(tr.k.sum()), int(np.sum(tr.status == ST_ENDED)),
+                     _lse(tr.lw), _lse(2 * tr.lw), _lse(tr.lw + lnk), _lse(tr.lw + 2 * lnk),
+                     float(kf.sum()), float((kf * kf).sum()), n_per_sub)

@@ -1,0 +1,485 @@
+/*
+ * fpt_oracle.c -- plain CPU oracle for the importance-sampled first-passage
+ * simulation of stochastic inflation (Jackson, Assadullahi, Koyama, Vennin,
+ * Wands, "Numerical simulations of stochastic inflation using importance
+ * sampling", arXiv:2206.11234).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product library links, includes
+ * or calls this file; only the tests, the smoke check and the CPU-baseline
+ * leg of the benchmark load it.  It shares no code with the GPU path.
+ *
+ * What it computes, one trajectory at a time, in the paper's order:
+ *   - the Euler-Maruyama step of the biased Langevin equation
+ *     (Sec. 2.2, eq. eq_euler_maruyam_modified), with drift D = -V'/V and
+ *     noise amplitude S = sqrt(V/3)/(2 pi) in Planck units (Sec. 2.3,
+ *     eq. eq_sr_diffusion with H^2 = V/3);
+ *   - the running exponent of the importance weight (Sec. 2.2,
+ *     eq. eq_importance_sampling_bias_w).  The exponent is accumulated with
+ *     a MINUS sign: substituting the two Gaussian path densities
+ *     (eqs. eq_importance_sampling_probability_of_target_path and
+ *     eq_importance_sampling_probability_of_sample_path) into the weight
+ *     ratio gives ln w = -sum (B/S^2)[B dt/2 + S xi sqrt(dt)]; the printed
+ *     equation drops that sign.  E_S[w] = 1 (tested) fixes it;
+ *   - repetition until the end surface phi_end is reached, recording the
+ *     elapsed number of steps k, so that N = k dN exactly (Sec. 2.1);
+ *   - a reflecting wall at phi_UV (Sec. 2.3, eq. eq:meanN:S:gen and the
+ *     discussion of the UV boundary in Sec. 3).
+ *
+ * Readings where the paper is silent (each is listed in the design notes):
+ *   - drift, noise amplitude and bias are evaluated at the pre-step point
+ *     (Ito, Sec. 2.1);
+ *   - the weight includes the crossing step (product over m = 0..M-1);
+ *   - the end test phi <= phi_end is applied after the reflection;
+ *   - a step cap k_max and (without a wall) an escape level phi_esc stop
+ *     runs that would not terminate; such runs are reported, not dropped.
+ *
+ * Two arithmetic modes over the SAME noise stream:
+ *   MODE_F32 -- every step in IEEE binary32, written operation by operation
+ *               with explicit fmaf, no contraction (build with
+ *               -ffp-contract=off), with the transcendental functions of the
+ *               normal transform written out below (so that the integer step
+ *               count is decided in binary32);
+ *   MODE_F64 -- the same semantics in binary64 with libm transcendentals,
+ *               used to state the binary32 error of every result.
+ *
+ * Noise: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random numbers:
+ * as easy as 1, 2, 3", SC'11), counter (k/4, t_lo, t_hi, stream), key
+ * (seed_lo, seed_hi); each 32-bit word x gives the uniform
+ * u = (2*(x>>9)+1) * 2^-24 in (0,1), and the Box-Muller transform maps
+ * (u0,u1) and (u2,u3) to four standard normals for steps 4j .. 4j+3:
+ * rho = sqrt(-2 ln u_a), z = rho cos(2 pi u_b), z' = rho sin(2 pi u_b).
+ */
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* ------------------------------------------------------------------ */
+/* Philox4x32-10 (SC'11): multipliers and Weyl key increments.          */
+/* ------------------------------------------------------------------ */
+#define PHILOX_M0 0xD2511F53u
+#define PHILOX_M1 0xCD9E8D57u
+#define PHILOX_W0 0x9E3779B9u
+#define PHILOX_W1 0xBB67AE85u
+
+void oracle_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t c0 = ctr[0], c1 = ctr[1], c2 = ctr[2], c3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_W0;
+            k1 += PHILOX_W1;
+        }
+        uint64_t p0 = (uint64_t)PHILOX_M0 * (uint64_t)c0;
+        uint64_t p1 = (uint64_t)PHILOX_M1 * (uint64_t)c2;
+        uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+        uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+        uint32_t n0 = hi1 ^ c1 ^ k0;
+        uint32_t n1 = lo1;
+        uint32_t n2 = hi0 ^ c3 ^ k1;
+        uint32_t n3 = lo0;
+        c0 = n0; c1 = n1; c2 = n2; c3 = n3;
+    }
+    out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
+}
+
+/* u = (2*(x>>9)+1) * 2^-24: an odd multiple of 2^-24, exact in binary32. */
+float oracle_uniform24(uint32_t x)
+{
+    uint32_t odd = ((x >> 9) << 1) | 1u;
+    return (float)odd * 0x1p-24f;
+}
+
+static float bits_to_f32(uint32_t b) { float f; memcpy(&f, &b, 4); return f; }
+static uint32_t f32_to_bits(float f) { uint32_t b; memcpy(&b, &f, 4); return b; }
+
+/* ------------------------------------------------------------------ */
+/* binary32 natural logarithm for positive normal inputs.               */
+/* Method: x = 2^e f with f in [sqrt(1/2), sqrt(2)); s = (f-1)/(f+1);   */
+/* ln f = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + s^7/7 + s^9/9 + ...);     */
+/* ln x = e ln2 + ln f with ln2 split in a 16-bit head and a tail.      */
+/* |s| <= 0.1716, so the first omitted term is below 1e-9 relative.    */
+/* ------------------------------------------------------------------ */
+float oracle_log_f32(float x)
+{
+    uint32_t b = f32_to_bits(x);
+    int e = (int)(b >> 23) - 127;
+    float f = bits_to_f32((b & 0x007FFFFFu) | 0x3F800000u); /* [1,2) */
+    if (f > 1.41421354f) {                                    /* fl32(sqrt 2) */
+        f = bits_to_f32((b & 0x007FFFFFu) | 0x3F000000u);     /* f/2, exact */
+        e += 1;
+    }
+    float s = (f - 1.0f) / (f + 1.0f);
+    float z = s * s;
+    float p = 1.0f / 9.0f;
+    p = fmaf(p, z, 1.0f / 7.0f);
+    p = fmaf(p, z, 1.0f / 5.0f);
+    p = fmaf(p, z, 1.0f / 3.0f);
+    float t = s + s;           /* 2s, exact */
+    float tz = t * z;
+    float lf = fmaf(tz, p, t); /* 2s + 2s z P(z) */
+    float ef = (float)e;
+    const float ln2_hi = 0.693145751953125f;       /* 16 significant bits */
+    const float ln2_lo = 1.42860682030941723212e-6f; /* ln 2 - ln2_hi */
+    return fmaf(ef, ln2_hi, fmaf(ef, ln2_lo, lf));
+}
+
+/* ------------------------------------------------------------------ */
+/* binary32 cos(2 pi u) and sin(2 pi u) for u in [0,1], u a multiple of */
+/* 2^-24.  q = nearest quarter, r = u - q/4 in [-1/8,1/8] (exact);      */
+/* Taylor series of sin(2 pi r) to r^9 and cos(2 pi r) to r^10 with     */
+/* coefficients (+-)(2 pi)^n / n!; the quadrant q rotates the pair.     */
+/* ------------------------------------------------------------------ */
+void oracle_sincos2pi_f32(float u, float *c_out, float *s_out)
+{
+    float q = rintf(u * 4.0f);
+    float r = u - q * 0.25f;
+    float r2 = r * r;
+    /* sin(2 pi r) = r (S1 + r2 (S3 + r2 (S5 + r2 (S7 + r2 S9)))) */
+    const float S1 = 6.28318530717958647692f;      /*  (2pi)^1/1!  */
+    const float S3 = -41.341702240399760234f;     /* -(2pi)^3/3!  */
+    const float S5 = 81.6052492760750542034f;      /*  (2pi)^5/5!  */
+    const float S7 = -76.7058597530613858416f;     /* -(2pi)^7/7!  */
+    const float S9 = 42.058693944897653145f;      /*  (2pi)^9/9!  */
+    const float C2 = -19.7392088021787172377f;     /* -(2pi)^2/2!  */
+    const float C4 = 64.939394022668291491f;      /*  (2pi)^4/4!  */
+    const float C6 = -85.456817206693727736f;     /* -(2pi)^6/6!  */
+    const float C8 = 60.2446413718766603627f;      /*  (2pi)^8/8!  */
+    const float C10 = -26.4262567833743974529f;    /* -(2pi)^10/10! */
+    float ps = fmaf(S9, r2, S7);
+    ps = fmaf(ps, r2, S5);
+    ps = fmaf(ps, r2, S3);
+    ps = fmaf(ps, r2, S1);
+    float sn = ps * r;
+    float pc = fmaf(C10, r2, C8);
+    pc = fmaf(pc, r2, C6);
+    pc = fmaf(pc, r2, C4);
+    pc = fmaf(pc, r2, C2);
+    float cs = fmaf(pc, r2, 1.0f);
+    int iq = ((int)q) & 3;
+    float c, s;
+    switch (iq) {
+    case 0: c = cs;  s = sn;  break;
+    case 1: c = -sn; s = cs;  break;
+    case 2: c = -cs; s = -sn; break;
+    default: c = sn; s = -cs; break;
+    }
+    *c_out = c;
+    *s_out = s;
+}
+
+/* ------------------------------------------------------------------ */
+/* binary32 exp(x) for x <= 0 (used by the Gaussian-bump potential).    */
+/* x < -80 gives 0.  n = rint(x/ln2); r = x - n ln2 (two-part ln2);     */
+/* Taylor series of e^r to r^7 (|r| <= 0.347: omitted term < 6e-9);     */
+/* result = P(r) * 2^n built from the exponent field.                   */
+/* ------------------------------------------------------------------ */
+float oracle_exp_f32(float x)
+{
+    if (x < -80.0f) return 0.0f;
+    if (x > 0.0f) x = 0.0f;
+    const float inv_ln2 = 1.44269504088896340736f;
+    const float ln2_hi = 0.693145751953125f;
+    const float ln2_lo = 1.42860682030941723212e-6f;
+    float n = rintf(x * inv_ln2);
+    float r = fmaf(-n, ln2_hi, x);
+    r = fmaf(-n, ln2_lo, r);
+    float p = 1.0f / 5040.0f;
+    p = fmaf(p, r, 1.0f / 720.0f);
+    p = fmaf(p, r, 1.0f / 120.0f);
+    p = fmaf(p, r, 1.0f / 24.0f);
+    p = fmaf(p, r, 1.0f / 6.0f);
+    p = fmaf(p, r, 0.5f);
+    p = fmaf(p, r, 1.0f);
+    p = fmaf(p, r, 1.0f);
+    int ni = (int)n;
+    float scale = bits_to_f32((uint32_t)(ni + 127) << 23);
+    return p * scale;
+}
+
+/* Four normals for steps 4j .. 4j+3 of trajectory t in stream `stream`. */
+void oracle_normals_f32(uint64_t seed, uint32_t stream, uint64_t t, uint32_t j, float out[4])
+{
+    uint32_t ctr[4] = { j, (uint32_t)t, (uint32_t)(t >> 32), stream };
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t x[4];
+    oracle_philox4x32_10(ctr, key, x);
+    for (int pair = 0; pair < 2; ++pair) {
+        float ua = oracle_uniform24(x[2 * pair]);
+        float ub = oracle_uniform24(x[2 * pair + 1]);
+        float L = oracle_log_f32(ua);
+        float rho = sqrtf(-2.0f * L);
+        float c, s;
+        oracle_sincos2pi_f32(ub, &c, &s);
+        out[2 * pair] = rho * c;
+        out[2 * pair + 1] = rho * s;
+    }
+}
+
+/* The same four normals in binary64 with libm (reference mode). */
+void oracle_normals_f64(uint64_t seed, uint32_t stream, uint64_t t, uint32_t j, double out[4])
+{
+    uint32_t ctr[4] = { j, (uint32_t)t, (uint32_t)(t >> 32), stream };
+    uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
+    uint32_t x[4];
+    oracle_philox4x32_10(ctr, key, x);
+    const double two_pi = 6.283185307179586476925;
+    for (int pair = 0; pair < 2; ++pair) {
+        double ua = (double)oracle_uniform24(x[2 * pair]);
+        double ub = (double)oracle_uniform24(x[2 * pair + 1]);
+        double rho = sqrt(-2.0 * log(ua));
+        out[2 * pair] = rho * cos(two_pi * ub);
+        out[2 * pair + 1] = rho * sin(two_pi * ub);
+    }
+}
+
+/* ------------------------------------------------------------------ */
+/* Model description.                                                   */
+/* ------------------------------------------------------------------ */
+enum { POT_QUADRATIC = 0, POT_QUADRATIC_BUMP = 1, POT_FLAT = 2 };
+enum { BIAS_NONE = 0, BIAS_NOISE_SCALED = 1, BIAS_POWER = 2 };
+enum { ST_RUNNING = 0, ST_ENDED = 1, ST_CENSORED = 2, ST_ESCAPED = 3 };
+enum { MODE_F32 = 0, MODE_F64 = 1 };
+
+/* All fields are the user's binary64 values; MODE_F32 rounds each of the
+ * derived constants below to binary32 once, MODE_F64 keeps them. */
+typedef struct {
+    int pot_kind;
+    double m, a, phi0, w, V0;   /* V = m^2 phi^2/2 [1 + a exp(-(phi-phi0)^2/(2w^2))], or V0 */
+    int bias_kind;
+    double A;                   /* B = A S (noise-scaled) or B = A phi^p (power law) */
+    int p;
+    double phi_in, phi_end, phi_uv, phi_esc, dN;
+    uint64_t k_max;
+    uint64_t seed;
+    uint32_t stream;
+} oracle_params;
+
+/* Derived constants (Planck units):
+ *   quadratic:  D = -2/phi,  S = c_m phi,  c_m = m/(2 pi sqrt 6)
+ *   bump:       V'/V = 2/phi - ((phi-phi0)/w^2) a g/(1 + a g),
+ *               g = exp(-(phi-phi0)^2/(2 w^2)),  S = c_m phi sqrt(1 + a g)
+ *   flat:       D = 0,  S = sqrt(V0/3)/(2 pi)                           */
+static double cm_of(double m) { return m / (2.0 * M_PI * sqrt(6.0)); }
+static double s_flat_of(double V0) { return sqrt(V0 / 3.0) / (2.0 * M_PI); }
+
+typedef struct {
+    float dN, sq, hdN, cm, s_flat, a, phi0, inv_w2, inv_2w2, A, phi_end, phi_uv, two_uv, phi_esc, phi_in;
+} consts_f32;
+
+static void make_consts_f32(const oracle_params *P, consts_f32 *c)
+{
+    c->dN = (float)P->dN;
+    c->sq = (float)sqrt(P->dN);
+    c->hdN = (float)(0.5 * P->dN);
+    c->cm = (float)cm_of(P->m);
+    c->s_flat = (float)s_flat_of(P->V0);
+    c->a = (float)P->a;
+    c->phi0 = (float)P->phi0;
+    c->inv_w2 = (float)(1.0 / (P->w * P->w));
+    c->inv_2w2 = (float)(0.5 / (P->w * P->w));
+    c->A = (float)P->A;
+    c->phi_end = (float)P->phi_end;
+    c->phi_uv = (float)P->phi_uv;
+    c->two_uv = c->phi_uv + c->phi_uv;
+    c->phi_esc = (float)P->phi_esc;
+    c->phi_in = (float)P->phi_in;
+}
+
+/* D and S at phi, binary32, operation by operation. */
+static void drift_noise_f32(const oracle_params *P, const consts_f32 *c, float phi, float *D, float *S)
+{
+    if (P->pot_kind == POT_QUADRATIC) {
+        float d = 2.0f / phi;
+        *D = -d;
+        *S = c->cm * phi;
+    } else if (P->pot_kind == POT_QUADRATIC_BUMP) {
+        float dphi = phi - c->phi0;
+        float e2 = dphi * dphi;
+        float x = -(e2 * c->inv_2w2);
+        float g = oracle_exp_f32(x);
+        float ag = c->a * g;
+        float one_ag = 1.0f + ag;
+        float num = (dphi * c->inv_w2) * ag;
+        float corr = num / one_ag;
+        float d = 2.0f / phi;
+        *D = corr - d;
+        *S = (c->cm * phi) * sqrtf(one_ag);
+    } else {
+        *D = 0.0f;
+        *S = c->s_flat;
+    }
+}
+
+/* r = B/S in noise units, binary32. */
+static float bias_ratio_f32(const oracle_params *P, const consts_f32 *c, float phi, float S)
+{
+    if (P->bias_kind == BIAS_NOISE_SCALED) return c->A;
+    if (P->bias_kind == BIAS_POWER) {
+        float pw = 1.0f;
+        for (int i = 0; i < P->p; ++i) pw = pw * phi;
+        return (c->A * pw) / S;
+    }
+    return 0.0f;
+}
+
+static void drift_noise_f64(const oracle_params *P, double phi, double *D, double *S)
+{
+    if (P->pot_kind == POT_QUADRATIC) {
+        *D = -2.0 / phi;
+        *S = cm_of(P->m) * phi;
+    } else if (P->pot_kind == POT_QUADRATIC_BUMP) {
+        double dphi = phi - P->phi0;
+        double g = exp(-dphi * dphi / (2.0 * P->w * P->w));
+        double ag = P->a * g;
+        *D = (dphi / (P->w * P->w)) * ag / (1.0 + ag) - 2.0 / phi;
+        *S = cm_of(P->m) * phi * sqrt(1.0 + ag);
+    } else {
+        *D = 0.0;
+        *S = s_flat_of(P->V0);
+    }
+}
+
+static double bias_ratio_f64(const oracle_params *P, double phi, double S)
+{
+    if (P->bias_kind == BIAS_NOISE_SCALED) return P->A;
+    if (P->bias_kind == BIAS_POWER) return P->A * pow(phi, (double)P->p) / S;
+    return 0.0;
+}
+
+/* One trajectory, binary32 mirror.  Returns the status; writes k, ln w and
+ * the final field value. */
+static int simulate_f32(const oracle_params *P, const consts_f32 *c, uint64_t t,
+                        uint64_t *k_out, double *lw_out, double *phi_out)
+{
+    float phi = c->phi_in;
+    double lw = 0.0;
+    uint64_t k = 0;
+    float xi4[4];
+    int status = ST_RUNNING;
+    while (status == ST_RUNNING) {
+        if ((k & 3u) == 0) oracle_normals_f32(P->seed, P->stream, t, (uint32_t)(k >> 2), xi4);
+        float xi = xi4[k & 3u];
+        float D, S;
+        drift_noise_f32(P, c, phi, &D, &S);
+        float r = bias_ratio_f32(P, c, phi, S);
+        float B = r * S;
+        float drift = D + B;
+        float det = fmaf(drift, c->dN, phi);
+        float amp = S * c->sq;
+        float nphi = fmaf(amp, xi, det);
+        float inc = fmaf(r, c->hdN, c->sq * xi);
+        float dlw = -(r * inc);
+        lw += (double)dlw;
+        if (nphi > c->phi_uv) nphi = c->two_uv - nphi;
+        phi = nphi;
+        k += 1;
+        if (phi <= c->phi_end) status = ST_ENDED;
+        else if (k >= P->k_max) status = ST_CENSORED;
+        else if (phi > c->phi_esc) status = ST_ESCAPED;
+    }
+    *k_out = k;
+    *lw_out = lw;
+    *phi_out = (double)phi;
+    return status;
+}
+
+/* One trajectory, binary64 reference on the same uniforms. */
+static int simulate_f64(const oracle_params *P, uint64_t t, uint64_t *k_out, double *lw_out, double *phi_out)
+{
+    double phi = P->phi_in;
+    double lw = 0.0;
+    uint64_t k = 0;
+    double xi4[4];
+    const double sq = sqrt(P->dN);
+    int status = ST_RUNNING;
+    while (status == ST_RUNNING) {
+        if ((k & 3u) == 0) oracle_normals_f64(P->seed, P->stream, t, (uint32_t)(k >> 2), xi4);
+        double xi = xi4[k & 3u];
+        double D, S;
+        drift_noise_f64(P, phi, &D, &S);
+        double r = bias_ratio_f64(P, phi, S);
+        double nphi = phi + (D + r * S) * P->dN + S * sq * xi;
+        lw += -r * (0.5 * r * P->dN + sq * xi);
+        if (nphi > P->phi_uv) nphi = 2.0 * P->phi_uv - nphi;
+        phi = nphi;
+        k += 1;
+        if (phi <= P->phi_end) status = ST_ENDED;
+        else if (k >= P->k_max) status = ST_CENSORED;
+        else if (phi > P->phi_esc) status = ST_ESCAPED;
+    }
+    *k_out = k;
+    *lw_out = lw;
+    *phi_out = phi;
+    return status;
+}
+
+/* Simulate trajectories t0 .. t0+n-1 (every one of them, or every
+ * `stride`-th id when stride > 1: t = t0 + i*stride).  Outputs are indexed
+ * by i.  Returns the number of threads used. */
+int oracle_simulate(const oracle_params *P, uint64_t t0, uint64_t stride, uint64_t n, int mode,
+                    uint64_t *k_out, double *lw_out, double *phi_out, int32_t *status_out,
+                    int n_threads)
+{
+    consts_f32 c;
+    make_consts_f32(P, &c);
+    if (stride == 0) stride = 1;
+    int used = 1;
+#ifdef _OPENMP
+    if (n_threads <= 0) n_threads = omp_get_max_threads();
+    used = n_threads;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(n_threads)
+#endif
+    for (int64_t i = 0; i < (int64_t)n; ++i) {
+        uint64_t t = t0 + (uint64_t)i * stride;
+        int st;
+        if (mode == MODE_F32)
+            st = simulate_f32(P, &c, t, &k_out[i], &lw_out[i], &phi_out[i]);
+        else
+            st = simulate_f64(P, t, &k_out[i], &lw_out[i], &phi_out[i]);
+        status_out[i] = st;
+    }
+    return used;
+}
+
+/* Exposed for the pins: binary32 D, S and r at one field value. */
+void oracle_drift_noise_bias_f32(const oracle_params *P, float phi, float out[3])
+{
+    consts_f32 c;
+    make_consts_f32(P, &c);
+    float D, S;
+    drift_noise_f32(P, &c, phi, &D, &S);
+    out[0] = D;
+    out[1] = S;
+    out[2] = bias_ratio_f32(P, &c, phi, S);
+}
+
+/* Batch helpers for the exhaustive accuracy pins. */
+void oracle_log_f32_batch(const float *x, float *y, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) y[i] = oracle_log_f32(x[i]);
+}
+
+void oracle_sincos2pi_f32_batch(const float *u, float *c, float *s, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) oracle_sincos2pi_f32(u[i], &c[i], &s[i]);
+}
+
+void oracle_exp_f32_batch(const float *x, float *y, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) y[i] = oracle_exp_f32(x[i]);
+}
+
+void oracle_normals_f32_batch(uint64_t seed, uint32_t stream, uint64_t t, uint32_t j0, uint32_t nj, float *out)
+{
+    for (uint32_t j = 0; j < nj; ++j) oracle_normals_f32(seed, stream, t, j0 + j, out + 4 * (size_t)j);
+}
+
+void oracle_normals_f64_batch(uint64_t seed, uint32_t stream, uint64_t t, uint32_t j0, uint32_t nj, double *out)
+{
+    for (uint32_t j = 0; j < nj; ++j) oracle_normals_f64(seed, stream, t, j0 + j, out + 4 * (size_t)j);
+}

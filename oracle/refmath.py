@@ -1,0 +1,359 @@
+"""Binary64 reference mathematics that pins the simulation.
+
+TEST INFRASTRUCTURE ONLY (part of the oracle; never imported by the product).
+
+Contents, each citing the passage it follows:
+  * ``drift_noise`` -- D = -V'/V, S = sqrt(V/3)/(2 pi) (Sec. 2.3,
+    eq. eq_sr_diffusion with H^2 = V/3, Planck units), bias B = A f(phi)
+    (eq. eq_importance_sampling_amplitude_general) with f = S, and the power
+    law B = A_p phi^p (eq. eq_importance_sampling_amplitude_power_law).
+  * ``moments`` -- mean first-passage time as the double integral of
+    eq. eq:meanN:S:gen, and the variance from the same Green's function with
+    the source of the moment recursion.  The recursion follows from the
+    adjoint Fokker-Planck equation for the characteristic function
+    (App. A, eq. eq_chracteristic_function_partial_diff_eqn with the
+    boundary conditions eq_chracteristic_function_bc) and the moment formula
+    <N^n> = i^-n d^n chi/dt^n at t = 0 (end of App. B): expanding chi in t
+    gives L f_n = -n f_{n-1} with L = (S^2/2) d^2 + (D+B) d, f_n(phi_end) = 0,
+    f_n'(phi_UV) = 0.  The variance g = f_2 - f_1^2 then obeys
+    L g = -S^2 (f_1')^2 with the same boundary conditions (Ito product rule),
+    which avoids the cancellation of f_2 - f_1^2 when sigma << mean.
+  * ``sl_modes`` -- decay rates and amplitudes of the pole expansion
+    P(N) = sum a_n exp(-Lambda_n N) (Sec. 1, eq. eq_pdf_expansion_in_exponentials;
+    App. A, eq. eq_pdf_expansion_in_exponentials2), obtained as the
+    Sturm-Liouville problem (S^2/2) psi'' + D psi' = -Lambda psi with
+    psi(phi_end) = 0, psi'(phi_UV) = 0 by shooting.
+  * ``brownian_*`` -- the quantum well (constant V, Sec. 3): Brownian first
+    passage with an absorbing end and a reflecting wall.
+  * ``classical_*`` -- the drift-dominated limit: N_cl = int dphi/|D|
+    (Sec. 2.4) and the Gaussian of App. B with gamma = kappa = 0.
+  * ``lattice_gaussian_probs`` -- that Gaussian mapped onto the lattice
+    N = k dN of the simulation.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+from scipy import integrate, optimize, special
+
+from . import BIAS_NONE, BIAS_NOISE_SCALED, BIAS_POWER, POT_FLAT, POT_QUADRATIC, POT_QUADRATIC_BUMP, Model
+
+
+# --------------------------------------------------------------------------
+# Drift, noise amplitude and bias in binary64 (Sec. 2.3).
+# --------------------------------------------------------------------------
+def potential(model: Model, phi):
+    phi = np.asarray(phi, np.float64)
+    if model.pot == POT_QUADRATIC:
+        return 0.5 * model.m ** 2 * phi ** 2
+    if model.pot == POT_QUADRATIC_BUMP:
+        g = np.exp(-(phi - model.phi0) ** 2 / (2 * model.w ** 2))
+        return 0.5 * model.m ** 2 * phi ** 2 * (1.0 + model.a * g)
+    return np.full_like(phi, model.V0)
+
+
+def dpotential(model: Model, phi):
+    phi = np.asarray(phi, np.float64)
+    if model.pot == POT_QUADRATIC:
+        return model.m ** 2 * phi
+    if model.pot == POT_QUADRATIC_BUMP:
+        g = np.exp(-(phi - model.phi0) ** 2 / (2 * model.w ** 2))
+        dg = -(phi - model.phi0) / model.w ** 2 * g
+        return model.m ** 2 * phi * (1.0 + model.a * g) + 0.5 * model.m ** 2 * phi ** 2 * model.a * dg
+    return np.zeros_like(phi)
+
+
+def drift_noise(model: Model, phi, biased: bool = True):
+    """(D, S, B) at phi: D = -V'/V (from 3H^2 = V), S = H/(2 pi) = sqrt(V/3)/(2 pi)."""
+    V = potential(model, phi)
+    D = -dpotential(model, phi) / V
+    S = np.sqrt(V / 3.0) / (2.0 * np.pi)
+    if not biased or model.bias == BIAS_NONE:
+        B = np.zeros_like(S)
+    elif model.bias == BIAS_NOISE_SCALED:
+        B = model.A * S
+    elif model.bias == BIAS_POWER:
+        B = model.A * np.asarray(phi, np.float64) ** model.p
+    else:
+        raise ValueError("bias kind not supported by the reference math")
+    return D, S, B
+
+
+# --------------------------------------------------------------------------
+# Moments of N from the Green's function of L (eq. eq:meanN:S:gen).
+# --------------------------------------------------------------------------
+def _cell_integrals(g, h):
+    """E0 = int_0^h e^{g y} dy and E1 = int_0^h y e^{g y} dy, stable for any g h."""
+    gh = g * h
+    small = np.abs(gh) < 1e-3
+    with np.errstate(over="ignore", invalid="ignore", divide="ignore"):
+        e = np.exp(gh)
+        E0 = np.where(small, h * (1 + gh / 2 + gh ** 2 / 6 + gh ** 3 / 24), np.expm1(gh) / g)
+        E1 = np.where(small, h * h * (0.5 + gh / 3 + gh ** 2 / 8 + gh ** 3 / 30), (h * e - E0) / g)
+    return e, E0, E1
+
+
+def _green_derivative(x, psi_p, psi_p_mid, source):
+    """J(x_i) = int_{x_i}^{x_M} source(y) exp(Psi(y) - Psi(x_i)) dy, backward over the grid.
+
+    Per cell, dPsi = int Psi' (Simpson).  Where |dPsi| is small the source is taken linear
+    in x and Psi linear in x (exact exponential integral); where |dPsi| is large (drift-
+    dominated, the integrand lives within 1/|Psi'| of the cell's left end) the integral is
+    taken in the variable Psi with source/Psi' linear in Psi, which is exact in the
+    local-equilibrium limit J = source/|Psi'|."""
+    h = np.diff(x)
+    dpsi = h * (psi_p[:-1] + 4.0 * psi_p_mid + psi_p[1:]) / 6.0
+    stiff = np.abs(dpsi) > 0.5
+    s = source
+    with np.errstate(over="ignore", invalid="ignore", divide="ignore"):
+        # x-form: Psi(x_i + y) - Psi(x_i) = g y with g = dPsi/h
+        g = dpsi / h
+        e, E0x, E1x = _cell_integrals(g, h)
+        cx = s[:-1] * E0x + (s[1:] - s[:-1]) * E1x / h
+        # Psi-form: int_0^dPsi q(u) e^u du with q = source/Psi' linear in u
+        q = s / psi_p
+        E0p = np.expm1(dpsi)
+        E1p = dpsi * np.exp(dpsi) - E0p
+        cp = q[:-1] * E0p + (q[1:] - q[:-1]) * E1p / dpsi
+        contrib = np.where(stiff, cp, cx)
+        prop = np.exp(dpsi)
+    J = np.zeros_like(x)
+    for i in range(len(x) - 2, -1, -1):
+        J[i] = J[i + 1] * prop[i] + contrib[i]
+    return J
+
+
+def _trapz_cum(x, y):
+    out = np.zeros_like(x)
+    out[1:] = np.cumsum(0.5 * (y[1:] + y[:-1]) * np.diff(x))
+    return out
+
+
+@dataclass
+class Moments:
+    mean: float
+    var: float
+
+    @property
+    def std(self):
+        return math.sqrt(self.var)
+
+
+def _top(model: Model, biased: bool) -> float:
+    if np.isfinite(model.phi_uv):
+        return model.phi_uv
+    top = model.esc()
+    if biased and model.bias != BIAS_NONE:
+        # beyond the zero of D + B the sample process runs away; the mean is
+        # then finite only if that point is never reached in practice.
+        xs = np.geomspace(model.phi_end, top, 200001) if model.phi_end > 0 else np.linspace(model.phi_end, top, 200001)
+        D, S, B = drift_noise(model, xs)
+        pos = np.nonzero(D + B > 0)[0]
+        if pos.size:
+            top = min(top, 0.9 * xs[pos[0]] + 0.1 * model.phi_in) if xs[pos[0]] > model.phi_in else top
+    return top
+
+
+def moments(model: Model, biased: bool = False, n_grid: int = 400001, phi=None) -> Moments:
+    """Mean and variance of N for a start at phi (default phi_in).
+
+    biased=False: the target process (drift D); biased=True: the sample process
+    (drift D + B).  f_1' = J with source 2/S^2; g' = J with source 2 (f_1')^2.
+    The result is Richardson-extrapolated over grids of n and n/2 cells."""
+    phi = model.phi_in if phi is None else phi
+
+    def solve(n):
+        top = _top(model, biased)
+        if model.pot != POT_FLAT and model.phi_end > 0:
+            x = model.phi_end * np.exp(np.linspace(0.0, math.log(top / model.phi_end), n))
+        else:
+            x = np.linspace(model.phi_end, top, n)
+        D, S, B = drift_noise(model, x, biased)
+        psi_p = 2.0 * (D + B) / S ** 2
+        xm = 0.5 * (x[1:] + x[:-1])
+        Dm, Sm, Bm = drift_noise(model, xm, biased)
+        psi_pm = 2.0 * (Dm + Bm) / Sm ** 2
+        J1 = _green_derivative(x, psi_p, psi_pm, 2.0 / S ** 2)
+        f1 = _trapz_cum(x, J1)
+        Jg = _green_derivative(x, psi_p, psi_pm, 2.0 * J1 ** 2)
+        gv = _trapz_cum(x, Jg)
+        return np.interp(phi, x, f1), np.interp(phi, x, gv)
+
+    m_a, v_a = solve(n_grid)
+    m_b, v_b = solve((n_grid - 1) // 2 + 1)
+    # cell rule is second order in h for smooth integrands
+    mean = m_a + (m_a - m_b) / 3.0
+    var = v_a + (v_a - v_b) / 3.0
+    return Moments(float(mean), float(var))
+
+
+# --------------------------------------------------------------------------
+# Drift-dominated limit (Sec. 2.4 classical N; App. B Gaussian).
+# --------------------------------------------------------------------------
+def classical_N(model: Model, biased: bool = False, phi=None) -> float:
+    """N_cl = int_{phi_end}^{phi} dphi' / |D + B| (noise set to zero)."""
+    phi = model.phi_in if phi is None else phi
+    f = lambda x: 1.0 / abs(float(sum(drift_noise(model, x, biased)[::2])))
+    return integrate.quad(f, model.phi_end, phi, epsabs=0, epsrel=1e-13, limit=200)[0]
+
+
+def classical_var_quadratic(m: float, phi_in: float, phi_end: float) -> float:
+    """Drift-limit variance for V = m^2 phi^2/2: int S^2 (f_1')^2/|D| dphi with
+    f_1' = phi/2, S^2 = m^2 phi^2/(24 pi^2): m^2 (phi_in^6 - phi_end^6)/(1152 pi^2)."""
+    return m ** 2 * (phi_in ** 6 - phi_end ** 6) / (1152.0 * math.pi ** 2)
+
+
+def noise_free_em(model: Model, biased: bool = False):
+    """Euler-Maruyama with the noise set to zero, binary64: returns (k, tau) where k is
+    the step count at first passage and tau the crossing time of the polygonal path."""
+    phi = model.phi_in
+    k = 0
+    while True:
+        D, S, B = drift_noise(model, phi, biased)
+        nphi = phi + float(D + B) * model.dN
+        k += 1
+        if nphi <= model.phi_end:
+            tau = (k - 1) * model.dN + model.dN * (phi - model.phi_end) / (phi - nphi)
+            return k, tau
+        phi = nphi
+
+
+def lattice_gaussian_probs(mu: float, sigma: float, dN: float, edges, eps: float = 0.0):
+    """P(e_j < k dN <= e_{j+1}) when k = ceil((N_c + eps)/dN) and N_c ~ Normal(mu, sigma):
+    the Gaussian of App. B (gamma = kappa = 0) seen on the simulation's lattice; eps is
+    the slowdown of the discrete drift (noise-free EM crossing time minus N_cl)."""
+    edges = np.asarray(edges, np.float64)
+    K = np.floor(edges / dN + 1e-9)
+    # largest k with k dN <= e_j
+    K = np.where((K + 1) * dN <= edges, K + 1, K)
+    K = np.where(K * dN > edges, K - 1, K)
+    z = (K * dN - eps - mu) / sigma
+    cdf = special.ndtr(z)
+    return np.diff(cdf)
+
+
+# --------------------------------------------------------------------------
+# Quantum well (constant V, Sec. 3): Brownian first passage.
+# --------------------------------------------------------------------------
+BGK_BETA = -special.zeta(0.5) / math.sqrt(2.0 * math.pi)   # 0.5826: Broadie-Glasserman-Kou
+
+
+def brownian_mean(x: float, a: float, b: float, S: float) -> float:
+    """E[T] for dx = S dW from x, absorbing at a < x, reflecting at b > x: solves
+    (S^2/2) f'' = -1, f(a) = 0, f'(b) = 0."""
+    return (x - a) * (2.0 * (b - a) - (x - a)) / S ** 2
+
+
+def brownian_var(x: float, a: float, b: float, S: float) -> float:
+    """Var T for the same process: (S^2/2) g'' = -S^2 f'^2, g(a) = 0, g'(b) = 0."""
+    L = b - a
+    y = x - a
+    # f' = 2 (L - y)/S^2  ->  g'' = -2 f'^2 = -8 (L - y)^2 / S^4
+    # g'(y) = 8/(3 S^4) (L - y)^3 ; g(y) = 2/(3 S^4) (L^4 - (L - y)^4)
+    return 2.0 / (3.0 * S ** 4) * (L ** 4 - (L - y) ** 4)
+
+
+def brownian_density_wall(T, x: float, a: float, b: float, S: float, n_terms: int = 400):
+    """First-passage density with a reflecting wall: sum of the sine eigen-series
+    P(T) = sum_n c_n (S^2 k_n^2 / 2) sin(k_n (x - a)) exp(-S^2 k_n^2 T/2),
+    k_n = (2n+1) pi / (2L), c_n = 4/((2n+1) pi)."""
+    T = np.asarray(T, np.float64)
+    L = b - a
+    n = np.arange(n_terms)
+    kn = (2 * n + 1) * math.pi / (2 * L)
+    cn = 4.0 / ((2 * n + 1) * math.pi)
+    lam = 0.5 * S ** 2 * kn ** 2
+    terms = cn[None, :] * lam[None, :] * np.sin(kn[None, :] * (x - a)) * np.exp(-lam[None, :] * T[..., None])
+    return terms.sum(-1)
+
+
+def brownian_survival_wall(T, x: float, a: float, b: float, S: float, n_terms: int = 400):
+    T = np.asarray(T, np.float64)
+    L = b - a
+    n = np.arange(n_terms)
+    kn = (2 * n + 1) * math.pi / (2 * L)
+    cn = 4.0 / ((2 * n + 1) * math.pi)
+    lam = 0.5 * S ** 2 * kn ** 2
+    terms = cn[None, :] * np.sin(kn[None, :] * (x - a)) * np.exp(-lam[None, :] * T[..., None])
+    return terms.sum(-1)
+
+
+def levy_density(T, x: float, a: float, S: float):
+    """No wall, no drift: (x - a)/(S sqrt(2 pi T^3)) exp(-(x - a)^2/(2 S^2 T))."""
+    T = np.asarray(T, np.float64)
+    y = x - a
+    return y / (S * np.sqrt(2 * np.pi * T ** 3)) * np.exp(-y * y / (2 * S * S * T))
+
+
+# --------------------------------------------------------------------------
+# Pole expansion from the Sturm-Liouville problem (App. A).
+# --------------------------------------------------------------------------
+@dataclass
+class Modes:
+    lam: np.ndarray     # decay rates Lambda_n
+    amp: np.ndarray     # a_n(phi_in)
+
+
+def _scalar_drift_s2(model: Model):
+    """Scalar (D, S^2) of the target process with math-module arithmetic (fast path for ODEs)."""
+    four_pi2 = 4.0 * math.pi ** 2
+    if model.pot == POT_QUADRATIC:
+        m2 = model.m ** 2
+        return lambda x: (-2.0 / x, 0.5 * m2 * x * x / (3.0 * four_pi2))
+    if model.pot == POT_QUADRATIC_BUMP:
+        m2, a, p0, w2 = model.m ** 2, model.a, model.phi0, model.w ** 2
+
+        def f(x):
+            g = math.exp(-(x - p0) ** 2 / (2 * w2))
+            V = 0.5 * m2 * x * x * (1 + a * g)
+            dV = m2 * x * (1 + a * g) - 0.5 * m2 * x * x * a * (x - p0) / w2 * g
+            return -dV / V, V / (3.0 * four_pi2)
+        return f
+    s2 = model.V0 / (3.0 * four_pi2)
+    return lambda x: (0.0, s2)
+
+
+def _shoot(model: Model, lam: float, rtol=1e-12, dense=False):
+    """psi(phi_end) = 0, psi'(phi_end) = 1 integrated up to phi_UV; carries Psi and the
+    weighted integrals int rho psi and int rho psi^2 with rho = (2/S^2) e^Psi."""
+    ds2 = _scalar_drift_s2(model)
+
+    def rhs(x, y):
+        psi, dpsi, Psi, i1, i2 = y
+        D, S2 = ds2(x)
+        rho = 2.0 / S2 * math.exp(Psi)
+        return [dpsi, -2.0 / S2 * (D * dpsi + lam * psi), 2.0 * D / S2, rho * psi, rho * psi * psi]
+    h0 = (model.phi_uv - model.phi_end) * 1e-4
+    sol = integrate.solve_ivp(rhs, (model.phi_end, model.phi_uv), [0.0, 1.0, 0.0, 0.0, 0.0],
+                              method="DOP853", rtol=rtol, atol=1e-300, dense_output=dense,
+                              first_step=h0)
+    return sol
+
+
+def sl_modes(model: Model, n_modes: int = 3, lam_max: float | None = None, n_scan: int = 120) -> Modes:
+    """First n_modes (Lambda_n, a_n) for a finite reflecting wall."""
+    if not np.isfinite(model.phi_uv):
+        raise ValueError("the pole expansion needs a finite reflecting wall")
+    F = lambda lam: _shoot(model, lam, rtol=1e-10).y[1, -1]
+    if lam_max is None:
+        lam_max = 2.0
+    grid = np.geomspace(lam_max * 1e-4, lam_max, n_scan)
+    vals = np.array([F(l) for l in grid])
+    roots = []
+    for i in range(len(grid) - 1):
+        if np.sign(vals[i]) != np.sign(vals[i + 1]):
+            Fr = lambda lam: _shoot(model, lam).y[1, -1]
+            roots.append(optimize.brentq(Fr, grid[i], grid[i + 1], xtol=1e-15, rtol=1e-14))
+            if len(roots) == n_modes:
+                break
+    lams, amps = [], []
+    for lam in roots:
+        sol = _shoot(model, lam, dense=True)
+        i1, i2 = sol.y[3, -1], sol.y[4, -1]
+        c = i1 / i2
+        psi_in = sol.sol(model.phi_in)[0]
+        lams.append(lam)
+        amps.append(lam * c * psi_in)
+    return Modes(np.array(lams), np.array(amps))
