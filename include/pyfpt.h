@@ -1,0 +1,232 @@
+/*
+ * pyfpt.h -- C ABI of the MI355X (gfx950) importance-sampled first-passage
+ * engine for stochastic inflation.
+ *
+ * Method: Jackson, Assadullahi, Koyama, Vennin, Wands, "Numerical simulations
+ * of stochastic inflation using importance sampling" (arXiv:2206.11234).
+ *
+ *   - Each run integrates the slow-roll Langevin equation with the
+ *     Euler-Maruyama step of the BIASED equation (Sec. 2.2,
+ *     eq. eq_euler_maruyam_modified):
+ *         phi_{k+1} = phi_k + [D(phi_k) + B(phi_k)] dN + S(phi_k) sqrt(dN) xi_k,
+ *     D = -V'/V and S = sqrt(V/3)/(2 pi) in Planck units (Sec. 2.3,
+ *     eq. eq_sr_diffusion with H^2 = V/3).
+ *   - The importance weight w = p_T/p_S of the path (Sec. 2.2,
+ *     eqs. eq_importance_sampling_bias ... eq_importance_sampling_bias_w) is
+ *     carried as ln w = -sum_k r_k (r_k dN/2 + sqrt(dN) xi_k), r = B/S: the
+ *     likelihood ratio of the two Gaussian path densities (the exponent as
+ *     printed in eq_importance_sampling_bias_w lacks this minus sign).
+ *   - A run stops at first passage phi <= phi_end and records N = k dN
+ *     (Sec. 2.1); phi > phi_UV is reflected (Sec. 2.3, Sec. 3).
+ *   - Runs are binned in N (right-closed bins, Sec. 2.1
+ *     eq. eq_bin_pdf_reconstrcuted) and each bin accumulates the weighted
+ *     estimator's sums (Sec. 2.2 eq. eq_bin_pdf_reconstrcuted_weighted_naive),
+ *     the jackknife subsets (Sec. 2.1) and moments of ln w (Sec. 2.4).
+ *
+ * Step arithmetic is IEEE binary32; ln w and all per-bin sums are binary64
+ * with log-sum-exp merges (weights span far more than the binary32 range).
+ * Noise: Philox4x32-10 (Salmon et al., SC'11) with counter
+ * (k/4, t_lo, t_hi, stream) and key (seed_lo, seed_hi); each 32-bit word x
+ * gives u = (2 (x >> 9) + 1) 2^-24 and Box-Muller maps (u0,u1), (u2,u3) to
+ * the normals of steps 4j..4j+3: rho = sqrt(-2 ln u_a), (rho cos 2 pi u_b,
+ * rho sin 2 pi u_b).  A trajectory's result depends only on
+ * (seed, stream, t) and the instance: it is the same for every launch
+ * configuration.
+ *
+ * Conventions for every entry point:
+ *   - returns PYFPT_OK (0) or a negative PYFPT_E* code; never aborts, never
+ *     throws across the ABI; pyfpt_last_error() gives a message (per thread);
+ *   - host-side structs and arrays passed in are read during the call only;
+ *   - output buffers are owned by the caller; the library never frees them;
+ *   - device pointers refer to memory of the current HIP device;
+ *   - work is enqueued on opt->stream (a hipStream_t; NULL = null stream).
+ *     With host outputs the call returns after the stream has finished; with
+ *     device outputs it returns once the work is enqueued.
+ */
+#ifndef PYFPT_H
+#define PYFPT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ---- */
+#define PYFPT_OK 0
+#define PYFPT_EINVAL (-1)      /* invalid argument (message says which) */
+#define PYFPT_ENOMEM (-2)      /* device or host allocation failed, or workspace too small */
+#define PYFPT_EDEVICE (-3)     /* HIP runtime error (message carries hipGetErrorString) */
+#define PYFPT_EUNSUPPORTED (-4)
+
+/* ---- potentials V(phi), Planck units (Sec. 2.3, Sec. 3) ---- */
+#define PYFPT_POT_QUADRATIC 0        /* V = m^2 phi^2 / 2 (eq. eq_quadratic_inflation_potential) */
+#define PYFPT_POT_QUADRATIC_BUMP 1   /* V = m^2 phi^2/2 [1 + a exp(-(phi-phi0)^2/(2 w^2))] */
+#define PYFPT_POT_FLAT 2             /* V = V0: the quantum well of Sec. 3 (D = 0, S const) */
+
+/* ---- bias B(phi) (Sec. 2.3 eq. eq_importance_sampling_amplitude_general) ---- */
+#define PYFPT_BIAS_NONE 0            /* B = 0: direct sampling, w = 1 */
+#define PYFPT_BIAS_NOISE_SCALED 1    /* B = A S(phi): f = S, the paper's default */
+#define PYFPT_BIAS_POWER 2           /* B = A phi^p (eq. eq_importance_sampling_amplitude_power_law), p >= 0 integer */
+#define PYFPT_BIAS_MLP 3             /* B = r_theta(phi, k dN, N*) S: learned proposal, see pyfpt_mlp */
+
+/* ---- run status (dump) ---- */
+#define PYFPT_ST_ENDED 1             /* phi <= phi_end reached: N = k dN */
+#define PYFPT_ST_CENSORED 2          /* k reached k_max */
+#define PYFPT_ST_ESCAPED 3           /* no wall and phi > phi_esc */
+
+typedef struct pyfpt_potential {
+    int32_t kind;                    /* PYFPT_POT_* */
+    double m, a, phi0, w;            /* quadratic (m) and bump (a, phi0, w) parameters */
+    double V0;                       /* flat potential */
+} pyfpt_potential;
+
+/* Learned proposal: a 3 -> H -> H -> 1 tanh network giving r = B/S from
+ * (phi, k dN, N*), each input affinely normalised: in_i = (x_i - mean_i) * inv_scale_i.
+ * Weights are bfloat16 on the device, row-major W[out][in]; biases float.
+ * Layout of `params` (device memory): see pyfpt_mlp_layout(). */
+typedef struct pyfpt_mlp {
+    const void *params;              /* device pointer (bf16 weights + f32 biases, pyfpt_mlp_layout) */
+    int32_t hidden;                  /* H: 64 */
+    float in_mean[3], in_inv_scale[3];
+    float out_scale;                 /* r = out_scale * (network output) */
+} pyfpt_mlp;
+
+typedef struct pyfpt_bias {
+    int32_t kind;                    /* PYFPT_BIAS_* */
+    int32_t p;                       /* power-law exponent */
+    double A;                        /* amplitude (A or A_p) */
+    double target_N;                 /* N* for the learned proposal */
+    pyfpt_mlp mlp;                   /* used when kind == PYFPT_BIAS_MLP */
+} pyfpt_bias;
+
+/* Bins: n_bins right-closed bins (e_j, e_{j+1}] over strictly ascending
+ * binary64 edges (host array of n_bins + 1).  n_sub jackknife subsets:
+ * trajectory t belongs to subset t mod n_sub (Sec. 2.1; >= 2; 16 if 0). */
+typedef struct pyfpt_bins {
+    int32_t n_bins;
+    int32_t n_sub;
+    const double *edges;
+} pyfpt_bins;
+
+/* One instance of a batched run. */
+typedef struct pyfpt_instance {
+    pyfpt_potential pot;
+    pyfpt_bias bias;
+    double phi_in, phi_end;          /* phi_in > phi_end */
+    double phi_uv;                   /* reflecting wall; +INFINITY = none; phi_uv >= phi_in */
+    double phi_esc;                  /* escape level without a wall; 0 -> 100 phi_in */
+    double dN;                       /* step, > 0 */
+    uint64_t n_traj;                 /* runs t = 0 .. n_traj-1 */
+    uint64_t k_max;                  /* step cap, 1 .. 2^32-1; 0 -> 2^20 */
+    uint32_t stream;                 /* noise stream id (Philox counter word 3) */
+    uint32_t reserved;
+    double cost_hint;                /* expected steps per run for queue ordering; 0 -> k_max */
+    pyfpt_bins bins;
+} pyfpt_instance;
+
+/*
+ * Result of one instance: two caller-owned flat buffers (host memory, or
+ * device memory when on_device != 0), sized by pyfpt_result_layout.
+ * R = n_bins + 4 rows: rows 0..n_bins-1 are the bins, then underflow
+ * (N <= e_0), overflow (N > e_B), censored, escaped.  J = n_sub.
+ *
+ * counts (uint64):
+ *   count[R]           runs per row
+ *   jk_count[J][R]     runs per (subset, row)
+ *   n_traj, total_steps (sum of k over every run, censored included)
+ * values (double):
+ *   lse_w[R]           log sum w per row (-inf when empty)
+ *   lse_w2[R]          log sum w^2 per row
+ *   jk_lse_w[J][R]     log sum w per (subset, row)
+ *   mean_lnw[R], m2_lnw[R], m3_lnw[R], m4_lnw[R]
+ *                      mean and central moments (1/n) sum (ln w - mean)^j (NaN when empty)
+ *   log_p[B]           log P_hat_j = lse_w - log(e_{j+1} - e_j) - log n_traj
+ *   rel_err_jk[B]      jackknife relative error of P_hat_j (sd over subsets / sqrt J)
+ *   rel_err_kish[B]    sqrt(sum w^2/(sum w)^2 - 1/n_traj): delta-method relative error
+ *   lse_w_all, lse_w2_all, lse_wk, lse_wk2   log sum over all runs of w, w^2, w k, w k^2
+ *   sum_k2             sum of k^2 over all runs
+ */
+typedef struct pyfpt_result {
+    uint64_t *counts;
+    double *values;
+    int32_t on_device;
+} pyfpt_result;
+
+typedef struct pyfpt_layout {
+    uint64_t n_counts, n_values;     /* buffer lengths in elements */
+    uint64_t count, jk_count, n_traj, total_steps;
+    uint64_t lse_w, lse_w2, jk_lse_w, mean_lnw, m2_lnw, m3_lnw, m4_lnw;
+    uint64_t log_p, rel_err_jk, rel_err_kish;
+    uint64_t lse_w_all, lse_w2_all, lse_wk, lse_wk2, sum_k2;
+} pyfpt_layout;
+
+/* Per-trajectory record of runs t with t % stride == 0 and t / stride < n
+ * (device arrays of n entries per instance, instance i at offset i*n). */
+typedef struct pyfpt_dump {
+    uint64_t n, stride;              /* n = 0: no dump */
+    uint32_t *k;
+    double *lw;
+    float *phi;
+    int32_t *status;
+} pyfpt_dump;
+
+typedef struct pyfpt_options {
+    void *stream;                    /* hipStream_t; NULL = null stream */
+    int32_t block;                   /* threads per workgroup (64..1024, multiple of 64); 0 = autotune */
+    int32_t chunk;                   /* queue claim multiplier per wave (>= 1); 0 = autotune */
+    int32_t wg_per_cu;               /* persistent workgroups per CU; 0 = autotune */
+    int32_t use_graph;               /* capture the launch sequence in a hipGraph and replay it */
+    void *workspace;                 /* device scratch; NULL = library-managed */
+    size_t workspace_bytes;
+    pyfpt_dump dump;
+    uint64_t k_max;                  /* pyfpt_run only: step cap (0 -> 2^20) */
+    double phi_esc;                  /* pyfpt_run only: escape level (0 -> 100 phi_in) */
+    uint32_t stream_id;              /* pyfpt_run only: noise stream */
+    uint32_t reserved;
+    float *timing_ms;                /* if not NULL: [0] step kernel, [1] merge kernel (synchronises) */
+} pyfpt_options;
+
+/* Buffer sizes and offsets of one instance's result. */
+int pyfpt_result_layout(int32_t n_bins, int32_t n_sub, pyfpt_layout *out);
+
+/*
+ * Single instance (the paper's inputs: V via pot, phi_in, phi_end, phi_UV,
+ * dN, bias, number of runs; Sec. 2.3 and Sec. 3).
+ * EINVAL: NaN/Inf in finite fields; phi_in <= phi_end; phi_uv < phi_in;
+ * dN <= 0; edges not strictly ascending or not finite; n_bins < 1;
+ * n_sub == 1 or n_sub > 64; k_max >= 2^32; a zero or negative V on
+ * [phi_end, phi_uv].  n_traj = 0 returns OK with empty rows.  Censored or
+ * escaped runs are not errors.
+ */
+int pyfpt_run(const pyfpt_potential *pot, double phi_in, double phi_end, double phi_uv, double dN,
+              const pyfpt_bias *bias, uint64_t n_traj, uint64_t seed, const pyfpt_bins *bins,
+              pyfpt_result *out, const pyfpt_options *opt);
+
+/*
+ * Batch: n_inst instances (1..1024) in one persistent launch over a shared
+ * work queue ordered longest-expected-run first; out is an array of n_inst
+ * results.  All instances must share the potential kind and bias kind
+ * (otherwise EUNSUPPORTED), except that PYFPT_BIAS_NONE and
+ * PYFPT_BIAS_NOISE_SCALED mix (no bias is the noise-scaled bias with A = 0,
+ * with identical results).  Same validation as pyfpt_run per instance.
+ */
+int pyfpt_run_batch(const pyfpt_instance *inst, int32_t n_inst, uint64_t seed,
+                    pyfpt_result *out, const pyfpt_options *opt);
+
+/* Device workspace needed by pyfpt_run_batch for these instances and options
+ * (block/wg_per_cu as resolved; 0 fields take the defaults). */
+int pyfpt_workspace_size(const pyfpt_instance *inst, int32_t n_inst, const pyfpt_options *opt,
+                         size_t *bytes);
+
+/* Number of compute units of the current device (0 if none). */
+int pyfpt_device_cus(int32_t *cus);
+
+const char *pyfpt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PYFPT_H */

@@ -118,6 +118,14 @@ class Model:
     k_max: int = 1 << 20
     stream: int = 0
 
+    @staticmethod
+    def from_instance(inst) -> "Model":
+        """The oracle's description of a workload instance (same field names)."""
+        return Model(pot=inst.pot, m=inst.m, a=inst.a, phi0=inst.phi0, w=inst.w, V0=inst.V0,
+                     bias=inst.bias, A=inst.A, p=inst.p, phi_in=inst.phi_in, phi_end=inst.phi_end,
+                     phi_uv=inst.phi_uv, phi_esc=inst.phi_esc, dN=inst.dN, k_max=inst.k_max,
+                     stream=inst.stream)
+
     def esc(self) -> float:
         if np.isfinite(self.phi_uv):
             return float("inf")

@@ -1,0 +1,15 @@
+"""MI355X-native importance-sampled first-passage engine for stochastic inflation.
+
+Method: Jackson, Assadullahi, Koyama, Vennin, Wands, arXiv:2206.11234.
+The hot path (Euler-Maruyama stepping with a drift bias and its importance
+weight, first passage, weighted N-histogram with log-sum-exp merges) runs in
+hand-written HIP kernels for gfx950 behind the C ABI of include/pyfpt.h;
+this package is the thin Python binding over it.
+"""
+from ._lib import (BIAS_MLP, BIAS_NOISE_SCALED, BIAS_NONE, BIAS_POWER, POT_FLAT, POT_QUADRATIC,
+                   POT_QUADRATIC_BUMP, ST_CENSORED, ST_ENDED, ST_ESCAPED, PyfptError)
+from .api import Dump, Result, device_cus, layout, run, run_batch, run_single_abi
+
+__all__ = ["run", "run_batch", "run_single_abi", "layout", "device_cus", "Result", "Dump", "PyfptError",
+           "POT_QUADRATIC", "POT_QUADRATIC_BUMP", "POT_FLAT", "BIAS_NONE", "BIAS_NOISE_SCALED", "BIAS_POWER",
+           "BIAS_MLP", "ST_ENDED", "ST_CENSORED", "ST_ESCAPED"]

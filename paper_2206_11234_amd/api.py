@@ -1,0 +1,258 @@
+"""Python binding over the C ABI: argument marshalling only.
+
+Every step of the path (stepping, binning, merging, estimators) runs in the
+HIP kernels of libpyfpt.so.  PyTorch supplies device memory (results, dumps,
+workspace) and the stream; numpy views of the returned buffers are built
+after the stream has finished.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from . import _lib as L
+
+
+def _torch():
+    import torch
+    if not torch.cuda.is_available():
+        raise RuntimeError("paper_2206_11234_amd needs a HIP GPU (gfx950); no CPU path exists")
+    return torch
+
+
+def layout(n_bins: int, n_sub: int = 16) -> L.pyfpt_layout:
+    lay = L.pyfpt_layout()
+    L.check(L.load().pyfpt_result_layout(n_bins, n_sub, ctypes.byref(lay)))
+    return lay
+
+
+@dataclass
+class Result:
+    """Per-instance outputs (see the layout comment of include/pyfpt.h)."""
+    edges: np.ndarray
+    n_sub: int
+    counts: np.ndarray          # uint64 flat buffer
+    values: np.ndarray          # float64 flat buffer
+    lay: L.pyfpt_layout = field(repr=False)
+
+    def _c(self, off, n):
+        return self.counts[off:off + n]
+
+    def _v(self, off, n):
+        return self.values[off:off + n]
+
+    @property
+    def n_bins(self):
+        return len(self.edges) - 1
+
+    @property
+    def n_rows(self):
+        return self.n_bins + 4
+
+    @property
+    def count(self):
+        return self._c(self.lay.count, self.n_rows)
+
+    @property
+    def jk_count(self):
+        return self._c(self.lay.jk_count, self.n_sub * self.n_rows).reshape(self.n_sub, self.n_rows)
+
+    @property
+    def n_traj(self):
+        return int(self.counts[self.lay.n_traj])
+
+    @property
+    def total_steps(self):
+        return int(self.counts[self.lay.total_steps])
+
+    @property
+    def lse_w(self):
+        return self._v(self.lay.lse_w, self.n_rows)
+
+    @property
+    def lse_w2(self):
+        return self._v(self.lay.lse_w2, self.n_rows)
+
+    @property
+    def jk_lse_w(self):
+        return self._v(self.lay.jk_lse_w, self.n_sub * self.n_rows).reshape(self.n_sub, self.n_rows)
+
+    @property
+    def mean_lnw(self):
+        return self._v(self.lay.mean_lnw, self.n_rows)
+
+    @property
+    def m2_lnw(self):
+        return self._v(self.lay.m2_lnw, self.n_rows)
+
+    @property
+    def m3_lnw(self):
+        return self._v(self.lay.m3_lnw, self.n_rows)
+
+    @property
+    def m4_lnw(self):
+        return self._v(self.lay.m4_lnw, self.n_rows)
+
+    @property
+    def log_p(self):
+        return self._v(self.lay.log_p, self.n_bins)
+
+    @property
+    def rel_err_jk(self):
+        return self._v(self.lay.rel_err_jk, self.n_bins)
+
+    @property
+    def rel_err_kish(self):
+        return self._v(self.lay.rel_err_kish, self.n_bins)
+
+    @property
+    def lse_w_all(self):
+        return float(self.values[self.lay.lse_w_all])
+
+    @property
+    def lse_w2_all(self):
+        return float(self.values[self.lay.lse_w2_all])
+
+    @property
+    def lse_wk(self):
+        return float(self.values[self.lay.lse_wk])
+
+    @property
+    def lse_wk2(self):
+        return float(self.values[self.lay.lse_wk2])
+
+    @property
+    def sum_k2(self):
+        return float(self.values[self.lay.sum_k2])
+
+    def ess(self):
+        with np.errstate(invalid="ignore"):
+            return np.exp(2 * self.lse_w[:self.n_bins] - self.lse_w2[:self.n_bins])
+
+
+@dataclass
+class Dump:
+    k: np.ndarray
+    lw: np.ndarray
+    phi: np.ndarray
+    status: np.ndarray
+    stride: int
+
+
+def _f(obj, name, default=0.0):
+    return getattr(obj, name, default)
+
+
+def make_instance(inst, n_sub: int, keep: list) -> L.pyfpt_instance:
+    edges = np.ascontiguousarray(np.asarray(inst.edges, dtype=np.float64))
+    keep.append(edges)
+    I = L.pyfpt_instance()
+    I.pot = L.pyfpt_potential(int(_f(inst, "pot", 0)), float(_f(inst, "m", 1.0)), float(_f(inst, "a", 0.0)),
+                              float(_f(inst, "phi0", 0.0)), float(_f(inst, "w", 1.0)), float(_f(inst, "V0", 1.0)))
+    I.bias.kind = int(_f(inst, "bias", 0))
+    I.bias.p = int(_f(inst, "p", 1))
+    I.bias.A = float(_f(inst, "A", 0.0))
+    I.bias.target_N = float(_f(inst, "target_N", 0.0))
+    I.phi_in = float(inst.phi_in)
+    I.phi_end = float(inst.phi_end)
+    I.phi_uv = float(_f(inst, "phi_uv", math.inf))
+    I.phi_esc = float(_f(inst, "phi_esc", 0.0))
+    I.dN = float(inst.dN)
+    I.n_traj = int(inst.n_traj)
+    I.k_max = int(_f(inst, "k_max", 0))
+    I.stream = int(_f(inst, "stream", 0))
+    I.cost_hint = float(_f(inst, "cost_hint", 0.0))
+    I.bins = L.pyfpt_bins(len(edges) - 1, n_sub, edges.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return I
+
+
+def run_batch(instances, seed: int = 0, *, n_sub: int = 16, block: int = 0, chunk: int = 0, wg_per_cu: int = 0,
+              use_graph: bool = False, dump_n: int = 0, dump_stride: int = 1, timing: bool = False,
+              torch_workspace: bool = True):
+    """Run a batch of instances in one persistent launch.  Returns (results, dumps, timing_ms)."""
+    torch = _torch()
+    lib = L.load()
+    keep: list = []
+    n = len(instances)
+    arr = (L.pyfpt_instance * n)(*[make_instance(i, n_sub, keep) for i in instances])
+    dev = torch.device("cuda", torch.cuda.current_device())
+    stream = torch.cuda.current_stream()
+    lays, res_t, res = [], [], (L.pyfpt_result * n)()
+    for i, inst in enumerate(instances):
+        lay = layout(len(inst.edges) - 1, n_sub)
+        c = torch.empty(int(lay.n_counts), dtype=torch.int64, device=dev)
+        v = torch.empty(int(lay.n_values), dtype=torch.float64, device=dev)
+        lays.append(lay)
+        res_t.append((c, v))
+        res[i] = L.pyfpt_result(c.data_ptr(), v.data_ptr(), 1)
+    opt = L.pyfpt_options()
+    opt.stream = ctypes.c_void_p(stream.cuda_stream)
+    opt.block, opt.chunk, opt.wg_per_cu, opt.use_graph = block, chunk, wg_per_cu, int(use_graph)
+    dump_t = None
+    if dump_n:
+        dump_t = (torch.zeros(n * dump_n, dtype=torch.int32, device=dev),
+                  torch.zeros(n * dump_n, dtype=torch.float64, device=dev),
+                  torch.zeros(n * dump_n, dtype=torch.float32, device=dev),
+                  torch.zeros(n * dump_n, dtype=torch.int32, device=dev))
+        opt.dump = L.pyfpt_dump(dump_n, dump_stride, dump_t[0].data_ptr(), dump_t[1].data_ptr(),
+                                dump_t[2].data_ptr(), dump_t[3].data_ptr())
+    ws_t = None
+    if torch_workspace:
+        nbytes = ctypes.c_size_t(0)
+        L.check(lib.pyfpt_workspace_size(arr, n, ctypes.byref(opt), ctypes.byref(nbytes)))
+        ws_t = torch.empty(int(nbytes.value), dtype=torch.uint8, device=dev)
+        opt.workspace = ctypes.c_void_p(ws_t.data_ptr())
+        opt.workspace_bytes = int(nbytes.value)
+    tm = (ctypes.c_float * 2)()
+    if timing:
+        opt.timing_ms = tm
+    L.check(lib.pyfpt_run_batch(arr, n, int(seed), res, ctypes.byref(opt)))
+    stream.synchronize()
+    results = []
+    for i, inst in enumerate(instances):
+        c, v = res_t[i]
+        results.append(Result(np.asarray(inst.edges, np.float64), n_sub, c.cpu().numpy().view(np.uint64),
+                              v.cpu().numpy(), lays[i]))
+    dumps = None
+    if dump_n:
+        k, lw, phi, st = (t.cpu().numpy() for t in dump_t)
+        dumps = [Dump(k[i * dump_n:(i + 1) * dump_n].view(np.uint32), lw[i * dump_n:(i + 1) * dump_n],
+                      phi[i * dump_n:(i + 1) * dump_n], st[i * dump_n:(i + 1) * dump_n], dump_stride)
+                 for i in range(n)]
+    del ws_t
+    return results, dumps, (list(tm) if timing else None)
+
+
+def run(inst, seed: int = 0, **kw):
+    """Single instance through pyfpt_run_batch (one persistent launch)."""
+    results, dumps, tm = run_batch([inst], seed, **kw)
+    return results[0], (dumps[0] if dumps else None), tm
+
+
+def run_single_abi(inst, seed: int = 0, *, n_sub: int = 16, block: int = 512, chunk: int = 1, wg_per_cu: int = 2):
+    """The same instance through the pyfpt_run entry point (host result buffers)."""
+    _torch()
+    lib = L.load()
+    keep: list = []
+    I = make_instance(inst, n_sub, keep)
+    lay = layout(len(inst.edges) - 1, n_sub)
+    counts = np.zeros(int(lay.n_counts), np.uint64)
+    values = np.zeros(int(lay.n_values), np.float64)
+    res = L.pyfpt_result(counts.ctypes.data, values.ctypes.data, 0)
+    opt = L.pyfpt_options()
+    opt.block, opt.chunk, opt.wg_per_cu = block, chunk, wg_per_cu
+    opt.k_max = I.k_max
+    opt.phi_esc = I.phi_esc
+    opt.stream_id = I.stream
+    L.check(lib.pyfpt_run(ctypes.byref(I.pot), I.phi_in, I.phi_end, I.phi_uv, I.dN, ctypes.byref(I.bias), I.n_traj,
+                          int(seed), ctypes.byref(I.bins), ctypes.byref(res), ctypes.byref(opt)))
+    return Result(np.asarray(inst.edges, np.float64), n_sub, counts, values, lay)
+
+
+def device_cus() -> int:
+    n = ctypes.c_int32(0)
+    L.check(L.load().pyfpt_device_cus(ctypes.byref(n)))
+    return int(n.value)

@@ -1,0 +1,225 @@
+// fpt_device.h -- device-side arithmetic of one Euler-Maruyama step of the
+// biased slow-roll Langevin equation, for gfx950.
+//
+// Method: arXiv:2206.11234, Sec. 2.1-2.3.  Every binary32 operation below is
+// part of the step semantics shared with the CPU checker: the step count of a
+// run is decided in binary32, so the order of operations and the places where
+// fma is used are fixed (the library is built with -ffp-contract=off, IEEE
+// division and square root, no fast-math).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fpt {
+
+enum : int { POT_QUADRATIC = 0, POT_QUADRATIC_BUMP = 1, POT_FLAT = 2 };
+enum : int { BIAS_NONE = 0, BIAS_NOISE_SCALED = 1, BIAS_POWER = 2, BIAS_MLP = 3 };
+enum : int { ST_RUNNING = 0, ST_ENDED = 1, ST_CENSORED = 2, ST_ESCAPED = 3 };
+
+// ---------------------------------------------------------------------------
+// Counter-based noise: Philox4x32-10 (Salmon, Moraes, Dror, Shaw, SC'11).
+// Ten rounds of two 32x32->64 multiplies; the key advances by the Weyl
+// constants between rounds.  The key (the seed) is wave-uniform.
+// ---------------------------------------------------------------------------
+struct U4 {
+    uint32_t x, y, z, w;
+};
+
+__device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                             uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+        }
+        const uint32_t lo_a = 0xD2511F53u * c0;
+        const uint32_t hi_a = __umulhi(0xD2511F53u, c0);
+        const uint32_t lo_b = 0xCD9E8D57u * c2;
+        const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2);
+        const uint32_t n0 = hi_b ^ c1 ^ k0;
+        const uint32_t n2 = hi_a ^ c3 ^ k1;
+        c0 = n0;
+        c1 = lo_b;
+        c2 = n2;
+        c3 = lo_a;
+    }
+    return U4{c0, c1, c2, c3};
+}
+
+// u = (2 (x >> 9) + 1) 2^-24: odd multiples of 2^-24 in (0, 1), exact in binary32.
+__device__ __forceinline__ float uniform24(uint32_t x) {
+    const uint32_t odd = ((x >> 9) << 1) | 1u;
+    return static_cast<float>(odd) * 0x1p-24f;
+}
+
+// ln x for positive normal x: x = 2^e f, f in [sqrt(1/2), sqrt 2];
+// ln f = 2 atanh(s), s = (f-1)/(f+1), as the odd series to s^9;
+// ln x = e ln2_hi + (e ln2_lo + ln f).
+__device__ __forceinline__ float log_f32(float x) {
+    const uint32_t b = __float_as_uint(x);
+    int e = static_cast<int>(b >> 23) - 127;
+    const uint32_t mant = b & 0x007FFFFFu;
+    float f = __uint_as_float(mant | 0x3F800000u);
+    if (f > 1.41421354f) {
+        f = __uint_as_float(mant | 0x3F000000u);
+        e += 1;
+    }
+    const float s = (f - 1.0f) / (f + 1.0f);
+    const float z = s * s;
+    float p = 1.0f / 9.0f;
+    p = __builtin_fmaf(p, z, 1.0f / 7.0f);
+    p = __builtin_fmaf(p, z, 1.0f / 5.0f);
+    p = __builtin_fmaf(p, z, 1.0f / 3.0f);
+    const float t = s + s;
+    const float tz = t * z;
+    const float lf = __builtin_fmaf(tz, p, t);
+    const float ef = static_cast<float>(e);
+    const float ln2_hi = 0.693145751953125f;
+    const float ln2_lo = 1.42860682030941723212e-6f;
+    return __builtin_fmaf(ef, ln2_hi, __builtin_fmaf(ef, ln2_lo, lf));
+}
+
+// cos(2 pi u), sin(2 pi u) for u in [0, 1] a multiple of 2^-24: nearest quarter q,
+// r = u - q/4 in [-1/8, 1/8] (exact), Taylor polynomials of sin(2 pi r) to r^9 and
+// cos(2 pi r) to r^10 with coefficients (+-)(2 pi)^n/n!, then a quarter-turn rotation.
+__device__ __forceinline__ void sincos2pi_f32(float u, float &c_out, float &s_out) {
+    const float q = __builtin_rintf(u * 4.0f);
+    const float r = u - q * 0.25f;
+    const float r2 = r * r;
+    float ps = __builtin_fmaf(42.058693944897653145f, r2, -76.7058597530613858416f);
+    ps = __builtin_fmaf(ps, r2, 81.6052492760750542034f);
+    ps = __builtin_fmaf(ps, r2, -41.341702240399760234f);
+    ps = __builtin_fmaf(ps, r2, 6.28318530717958647692f);
+    const float sn = ps * r;
+    float pc = __builtin_fmaf(-26.4262567833743974529f, r2, 60.2446413718766603627f);
+    pc = __builtin_fmaf(pc, r2, -85.456817206693727736f);
+    pc = __builtin_fmaf(pc, r2, 64.939394022668291491f);
+    pc = __builtin_fmaf(pc, r2, -19.7392088021787172377f);
+    const float cs = __builtin_fmaf(pc, r2, 1.0f);
+    const int iq = static_cast<int>(q) & 3;
+    float c, s;
+    if (iq == 0) {
+        c = cs;
+        s = sn;
+    } else if (iq == 1) {
+        c = -sn;
+        s = cs;
+    } else if (iq == 2) {
+        c = -cs;
+        s = -sn;
+    } else {
+        c = sn;
+        s = -cs;
+    }
+    c_out = c;
+    s_out = s;
+}
+
+// e^x for x <= 0 (x < -80 gives 0): n = rint(x / ln 2), r = x - n ln2 (two-part),
+// Taylor series of e^r to r^7, times 2^n assembled in the exponent field.
+__device__ __forceinline__ float exp_f32(float x) {
+    const bool under = x < -80.0f;
+    if (x > 0.0f) x = 0.0f;
+    if (under) x = -80.0f;
+    const float n = __builtin_rintf(x * 1.44269504088896340736f);
+    float r = __builtin_fmaf(-n, 0.693145751953125f, x);
+    r = __builtin_fmaf(-n, 1.42860682030941723212e-6f, r);
+    float p = 1.0f / 5040.0f;
+    p = __builtin_fmaf(p, r, 1.0f / 720.0f);
+    p = __builtin_fmaf(p, r, 1.0f / 120.0f);
+    p = __builtin_fmaf(p, r, 1.0f / 24.0f);
+    p = __builtin_fmaf(p, r, 1.0f / 6.0f);
+    p = __builtin_fmaf(p, r, 0.5f);
+    p = __builtin_fmaf(p, r, 1.0f);
+    p = __builtin_fmaf(p, r, 1.0f);
+    const int ni = static_cast<int>(n);
+    const float scale = __uint_as_float(static_cast<uint32_t>(ni + 127) << 23);
+    const float y = p * scale;
+    return under ? 0.0f : y;
+}
+
+// Four standard normals for steps 4j .. 4j+3 of run t: Box-Muller on (u0,u1), (u2,u3).
+struct F4 {
+    float a, b, c, d;
+};
+
+__device__ __forceinline__ F4 normals4(uint32_t j, uint64_t t, uint32_t stream, uint32_t key0, uint32_t key1) {
+    const U4 x = philox4x32_10(j, static_cast<uint32_t>(t), static_cast<uint32_t>(t >> 32), stream, key0, key1);
+    F4 out;
+    {
+        const float ua = uniform24(x.x);
+        const float ub = uniform24(x.y);
+        const float rho = __builtin_sqrtf(-2.0f * log_f32(ua));
+        float c, s;
+        sincos2pi_f32(ub, c, s);
+        out.a = rho * c;
+        out.b = rho * s;
+    }
+    {
+        const float ua = uniform24(x.z);
+        const float ub = uniform24(x.w);
+        const float rho = __builtin_sqrtf(-2.0f * log_f32(ua));
+        float c, s;
+        sincos2pi_f32(ub, c, s);
+        out.c = rho * c;
+        out.d = rho * s;
+    }
+    return out;
+}
+
+// ---------------------------------------------------------------------------
+// Per-instance binary32 step constants (rounded once on the host from the
+// binary64 inputs).
+// ---------------------------------------------------------------------------
+struct StepConsts {
+    float dN, sq, hdN, cm;        // dN, sqrt dN, dN/2, m/(2 pi sqrt 6) (flat: S)
+    float a, phi0, inv_w2, inv_2w2;
+    float A, phi_end, phi_uv, two_uv;
+    float phi_esc, phi_in;
+    int32_t p;
+    uint32_t k_max;
+};
+
+// D = -V'/V and S = sqrt(V/3)/(2 pi) at phi (Sec. 2.3).
+template <int POT>
+__device__ __forceinline__ void drift_noise(const StepConsts &C, float phi, float &D, float &S) {
+    if constexpr (POT == POT_QUADRATIC) {
+        const float d = 2.0f / phi;
+        D = -d;
+        S = C.cm * phi;
+    } else if constexpr (POT == POT_QUADRATIC_BUMP) {
+        const float dphi = phi - C.phi0;
+        const float e2 = dphi * dphi;
+        const float x = -(e2 * C.inv_2w2);
+        const float g = exp_f32(x);
+        const float ag = C.a * g;
+        const float one_ag = 1.0f + ag;
+        const float num = (dphi * C.inv_w2) * ag;
+        const float corr = num / one_ag;
+        const float d = 2.0f / phi;
+        D = corr - d;
+        S = (C.cm * phi) * __builtin_sqrtf(one_ag);
+    } else {
+        D = 0.0f;
+        S = C.cm;
+    }
+}
+
+// r = B/S in noise units (Sec. 2.3 eq. eq_importance_sampling_amplitude_general
+// with f = S, and the power law of Sec. 3.4).
+template <int BIAS>
+__device__ __forceinline__ float bias_ratio(const StepConsts &C, float phi, float S) {
+    if constexpr (BIAS == BIAS_NOISE_SCALED) {
+        return C.A;
+    } else if constexpr (BIAS == BIAS_POWER) {
+        float pw = 1.0f;
+        for (int i = 0; i < C.p; ++i) pw = pw * phi;
+        return (C.A * pw) / S;
+    } else {
+        return 0.0f;
+    }
+}
+
+}  // namespace fpt

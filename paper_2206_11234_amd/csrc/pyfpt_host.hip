@@ -1,0 +1,734 @@
+// pyfpt_host.hip -- host runtime behind the C ABI of include/pyfpt.h.
+//
+// Per call: validate, turn each instance into binary32 step constants and
+// integer bin thresholds (Sec. 2.1 bins (e_j, e_{j+1}] of N = k dN become
+// K_j < k <= K_{j+1}), order the shared work queue longest-expected-run first,
+// upload, launch queue reset -> persistent step kernel -> merge -> finalize
+// on the caller's stream (optionally as a replayed hipGraph), and copy the
+// per-instance results out.  Launch shape (workgroup size, workgroups per CU,
+// queue claim chunk) comes from the options or from a measured autotuner
+// cached per device and workload signature.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "../../include/pyfpt.h"
+#include "fpt_kernels.h"
+
+using namespace fpt;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+int dev_fail(hipError_t e, const char *what) {
+    return fail(PYFPT_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define HIP_TRY(expr, what)                       \
+    do {                                          \
+        hipError_t e_ = (expr);                   \
+        if (e_ != hipSuccess) return dev_fail(e_, what); \
+    } while (0)
+
+constexpr uint64_t kDefaultKmax = 1ull << 20;
+constexpr int kDefaultNsub = 16;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+struct LaunchCfg {
+    int block = 0, wg_per_cu = 0, chunk = 0;
+};
+
+struct Device {
+    int id = -1;
+    int cus = 0;
+    size_t max_lds = 0;
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    void *pinned = nullptr;
+    size_t pinned_bytes = 0;
+    hipEvent_t pinned_done = nullptr;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    // graph cache
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    std::vector<unsigned char> gkey;
+    std::map<std::string, LaunchCfg> tuned;
+};
+
+std::mutex g_mu;
+std::map<int, Device> g_dev;
+
+int get_device(Device **out) {
+    int id = 0;
+    HIP_TRY(hipGetDevice(&id), "hipGetDevice");
+    Device &d = g_dev[id];
+    if (d.id < 0) {
+        d.id = id;
+        hipDeviceProp_t p;
+        HIP_TRY(hipGetDeviceProperties(&p, id), "hipGetDeviceProperties");
+        d.cus = p.multiProcessorCount;
+        int lds = 0;
+        if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, id) != hipSuccess) lds = 65536;
+        d.max_lds = static_cast<size_t>(lds);
+        HIP_TRY(hipEventCreateWithFlags(&d.pinned_done, hipEventDisableTiming), "hipEventCreate");
+        for (auto &e : d.ev) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+    }
+    *out = &d;
+    return PYFPT_OK;
+}
+
+bool finite(double x) { return std::isfinite(x); }
+
+// ----------------------------------------------------------------------------
+// validation and preparation
+// ----------------------------------------------------------------------------
+struct Prepared {
+    std::vector<InstDev> inst;
+    std::vector<uint32_t> order;
+    std::vector<uint64_t> vbeg_sorted;
+    std::vector<uint32_t> thr;
+    std::vector<double> edges;
+    std::vector<MergeInst> mi;
+    std::vector<ResultLayout> rl;
+    TableLayout lay{};
+    uint64_t v_total = 0;
+    uint64_t counts_total = 0, values_total = 0;
+    int pot = 0, bias = 0;
+    uint32_t n_sub = 0;
+};
+
+int check_f32(double x, const char *name, int i) {
+    const float f = static_cast<float>(x);
+    if (std::isnan(x) || (std::isinf(f) && !std::isinf(x)))
+        return fail(PYFPT_EINVAL, "instance %d: %s = %g not representable in binary32", i, name, x);
+    return PYFPT_OK;
+}
+
+int validate(const pyfpt_instance &I, int i) {
+    const pyfpt_potential &P = I.pot;
+    if (!finite(I.phi_in) || !finite(I.phi_end) || !finite(I.dN))
+        return fail(PYFPT_EINVAL, "instance %d: phi_in, phi_end and dN must be finite", i);
+    if (!(I.phi_in > I.phi_end)) return fail(PYFPT_EINVAL, "instance %d: need phi_in > phi_end", i);
+    if (std::isnan(I.phi_uv) || (std::isinf(I.phi_uv) && I.phi_uv < 0))
+        return fail(PYFPT_EINVAL, "instance %d: phi_uv must be a number or +inf", i);
+    if (I.phi_uv < I.phi_in) return fail(PYFPT_EINVAL, "instance %d: need phi_uv >= phi_in", i);
+    if (!(I.dN > 0)) return fail(PYFPT_EINVAL, "instance %d: need dN > 0", i);
+    if (std::isnan(I.phi_esc) || I.phi_esc < 0) return fail(PYFPT_EINVAL, "instance %d: bad phi_esc", i);
+    if (I.phi_esc != 0 && !(I.phi_esc > I.phi_in)) return fail(PYFPT_EINVAL, "instance %d: need phi_esc > phi_in", i);
+    if (I.k_max >= (1ull << 32)) return fail(PYFPT_EINVAL, "instance %d: k_max must be < 2^32", i);
+    switch (P.kind) {
+    case PYFPT_POT_QUADRATIC:
+    case PYFPT_POT_QUADRATIC_BUMP:
+        if (!finite(P.m) || !(P.m > 0)) return fail(PYFPT_EINVAL, "instance %d: need finite m > 0", i);
+        if (!(I.phi_end > 0)) return fail(PYFPT_EINVAL, "instance %d: quadratic potentials need phi_end > 0", i);
+        if (P.kind == PYFPT_POT_QUADRATIC_BUMP) {
+            if (!finite(P.a) || !finite(P.phi0) || !finite(P.w) || !(P.w > 0) || !(P.a > -1))
+                return fail(PYFPT_EINVAL, "instance %d: bump needs finite a > -1, phi0, w > 0", i);
+        }
+        break;
+    case PYFPT_POT_FLAT:
+        if (!finite(P.V0) || !(P.V0 > 0)) return fail(PYFPT_EINVAL, "instance %d: need finite V0 > 0", i);
+        break;
+    default:
+        return fail(PYFPT_EINVAL, "instance %d: unknown potential kind %d", i, P.kind);
+    }
+    const pyfpt_bias &B = I.bias;
+    switch (B.kind) {
+    case PYFPT_BIAS_NONE: break;
+    case PYFPT_BIAS_NOISE_SCALED:
+        if (!finite(B.A)) return fail(PYFPT_EINVAL, "instance %d: bias amplitude must be finite", i);
+        break;
+    case PYFPT_BIAS_POWER:
+        if (!finite(B.A) || B.p < 0 || B.p > 16) return fail(PYFPT_EINVAL, "instance %d: power bias needs finite A and 0 <= p <= 16", i);
+        break;
+    case PYFPT_BIAS_MLP:
+        return fail(PYFPT_EUNSUPPORTED, "instance %d: the learned proposal is run by pyfpt_run_mlp", i);
+    default:
+        return fail(PYFPT_EINVAL, "instance %d: unknown bias kind %d", i, B.kind);
+    }
+    const pyfpt_bins &bn = I.bins;
+    if (bn.n_bins < 1 || bn.n_bins > (1 << 20)) return fail(PYFPT_EINVAL, "instance %d: n_bins out of range", i);
+    if (bn.n_sub == 1 || bn.n_sub < 0 || bn.n_sub > 64) return fail(PYFPT_EINVAL, "instance %d: n_sub must be 0 or 2..64", i);
+    if (!bn.edges) return fail(PYFPT_EINVAL, "instance %d: edges is NULL", i);
+    for (int j = 0; j <= bn.n_bins; ++j) {
+        if (!finite(bn.edges[j])) return fail(PYFPT_EINVAL, "instance %d: edge %d not finite", i, j);
+        if (j > 0 && !(bn.edges[j] > bn.edges[j - 1])) return fail(PYFPT_EINVAL, "instance %d: edges not strictly ascending at %d", i, j);
+    }
+    int rc;
+    if ((rc = check_f32(I.phi_in, "phi_in", i)) || (rc = check_f32(I.phi_end, "phi_end", i)) ||
+        (rc = check_f32(I.dN, "dN", i)))
+        return rc;
+    if (finite(I.phi_uv) && (rc = check_f32(2.0 * I.phi_uv, "2 phi_uv", i))) return rc;
+    return PYFPT_OK;
+}
+
+uint32_t threshold(double e, double dN) {
+    // K = max{k >= 0 : fl(k * dN) <= e}, clamped to [0, 2^32-1]
+    if (e < 0) return 0;
+    double q = std::floor(e / dN);
+    if (q > 4294967294.0) return 0xFFFFFFFFu;
+    int64_t K = static_cast<int64_t>(q);
+    while (static_cast<double>(K + 1) * dN <= e) ++K;
+    while (K > 0 && static_cast<double>(K) * dN > e) --K;
+    if (K > 0xFFFFFFFFll) return 0xFFFFFFFFu;
+    return static_cast<uint32_t>(K);
+}
+
+double expected_steps(const pyfpt_instance &I, uint64_t k_max) {
+    if (I.cost_hint > 0) return std::min(I.cost_hint, static_cast<double>(k_max));
+    if (I.pot.kind == PYFPT_POT_QUADRATIC || I.pot.kind == PYFPT_POT_QUADRATIC_BUMP) {
+        const double ncl = (I.phi_in * I.phi_in - I.phi_end * I.phi_end) / 4.0;
+        return std::min(ncl / I.dN, static_cast<double>(k_max));
+    }
+    return static_cast<double>(k_max);
+}
+
+int prepare(const pyfpt_instance *ins, int n_inst, Prepared &P) {
+    if (n_inst < 1 || n_inst > 1024) return fail(PYFPT_EINVAL, "n_inst must be 1..1024");
+    for (int i = 0; i < n_inst; ++i) {
+        int rc = validate(ins[i], i);
+        if (rc) return rc;
+    }
+    P.pot = ins[0].pot.kind;
+    P.bias = ins[0].bias.kind;
+    // No bias is the noise-scaled bias with A = 0: the step then adds +0 to the drift and
+    // +-0 to ln w, so a batch mixing the two runs as noise-scaled with identical results.
+    for (int i = 1; i < n_inst; ++i) {
+        const int b = ins[i].bias.kind;
+        if (b != P.bias && ((b == PYFPT_BIAS_NONE && P.bias == PYFPT_BIAS_NOISE_SCALED) ||
+                            (b == PYFPT_BIAS_NOISE_SCALED && P.bias == PYFPT_BIAS_NONE)))
+            P.bias = PYFPT_BIAS_NOISE_SCALED;
+    }
+    const int ns0 = ins[0].bins.n_sub ? ins[0].bins.n_sub : kDefaultNsub;
+    for (int i = 1; i < n_inst; ++i) {
+        const int b = ins[i].bias.kind == PYFPT_BIAS_NONE && P.bias == PYFPT_BIAS_NOISE_SCALED
+                          ? PYFPT_BIAS_NOISE_SCALED : ins[i].bias.kind;
+        if (ins[i].pot.kind != P.pot || b != P.bias)
+            return fail(PYFPT_EUNSUPPORTED, "all instances of a batch must share potential and bias kinds");
+        const int ns = ins[i].bins.n_sub ? ins[i].bins.n_sub : kDefaultNsub;
+        if (ns != ns0) return fail(PYFPT_EINVAL, "all instances of a batch must share n_sub");
+    }
+    P.n_sub = static_cast<uint32_t>(ns0);
+    P.inst.resize(n_inst);
+    P.mi.resize(n_inst);
+    P.rl.resize(n_inst);
+    uint32_t rows = 0, thr_base = 0;
+    std::vector<std::pair<double, int>> cost;
+    for (int i = 0; i < n_inst; ++i) {
+        const pyfpt_instance &I = ins[i];
+        const uint64_t k_max = I.k_max ? I.k_max : kDefaultKmax;
+        InstDev &D = P.inst[i];
+        std::memset(&D, 0, sizeof D);
+        StepConsts &C = D.c;
+        C.dN = static_cast<float>(I.dN);
+        C.sq = static_cast<float>(std::sqrt(I.dN));
+        C.hdN = static_cast<float>(0.5 * I.dN);
+        if (I.pot.kind == PYFPT_POT_FLAT)
+            C.cm = static_cast<float>(std::sqrt(I.pot.V0 / 3.0) / (2.0 * M_PI));
+        else
+            C.cm = static_cast<float>(I.pot.m / (2.0 * M_PI * std::sqrt(6.0)));
+        C.a = static_cast<float>(I.pot.a);
+        C.phi0 = static_cast<float>(I.pot.phi0);
+        C.inv_w2 = static_cast<float>(1.0 / (I.pot.w * I.pot.w));
+        C.inv_2w2 = static_cast<float>(0.5 / (I.pot.w * I.pot.w));
+        C.A = I.bias.kind == PYFPT_BIAS_NONE ? 0.0f : static_cast<float>(I.bias.A);
+        C.p = I.bias.p;
+        C.phi_end = static_cast<float>(I.phi_end);
+        C.phi_uv = static_cast<float>(I.phi_uv);
+        C.two_uv = C.phi_uv + C.phi_uv;
+        const bool wall = std::isfinite(I.phi_uv);
+        C.phi_esc = wall ? INFINITY : static_cast<float>(I.phi_esc > 0 ? I.phi_esc : 100.0 * I.phi_in);
+        C.phi_in = static_cast<float>(I.phi_in);
+        C.k_max = static_cast<uint32_t>(k_max);
+        D.stream = I.stream;
+        D.n_bins = static_cast<uint32_t>(I.bins.n_bins);
+        D.row_base = rows;
+        D.thr_base = thr_base;
+        D.dump_slot = static_cast<uint32_t>(i);
+        D.n_traj = I.n_traj;
+        for (int j = 0; j <= I.bins.n_bins; ++j) {
+            P.thr.push_back(threshold(I.bins.edges[j], I.dN));
+            P.edges.push_back(I.bins.edges[j]);
+        }
+        MergeInst &M = P.mi[i];
+        M.row_base = rows;
+        M.n_rows = D.n_bins + 4;
+        M.n_bins = D.n_bins;
+        M.edge_base = thr_base;
+        M.n_traj = I.n_traj;
+        P.rl[i] = result_layout(D.n_bins, P.n_sub);
+        M.counts_off = P.counts_total;
+        M.values_off = P.values_total;
+        P.counts_total += P.rl[i].n_counts;
+        P.values_total += P.rl[i].n_values;
+        rows += D.n_bins + 4;
+        thr_base += D.n_bins + 1;
+        if (I.n_traj > 0) cost.push_back({expected_steps(I, k_max), i});
+    }
+    // longest expected runs first (ties: caller order)
+    std::stable_sort(cost.begin(), cost.end(), [](auto &a, auto &b) { return a.first > b.first; });
+    uint64_t v = 0;
+    for (auto &c : cost) {
+        P.order.push_back(static_cast<uint32_t>(c.second));
+        P.vbeg_sorted.push_back(v);
+        P.inst[c.second].v_begin = v;
+        v += ins[c.second].n_traj;
+    }
+    if (P.order.empty()) {
+        P.order.push_back(0);
+        P.vbeg_sorted.push_back(0);
+    }
+    P.v_total = v;
+    // per-workgroup table layout
+    TableLayout &L = P.lay;
+    L.n_rows = rows;
+    L.n_sub = P.n_sub;
+    L.n_inst = static_cast<uint32_t>(n_inst);
+    size_t off = 0;
+    L.off_scal = 0;
+    off = align_up(static_cast<size_t>(n_inst) * 64, 16);
+    L.off_jk_lse = static_cast<uint32_t>(off);
+    off += static_cast<size_t>(P.n_sub) * rows * 8;
+    L.off_lse_w2 = static_cast<uint32_t>(off);
+    off += static_cast<size_t>(rows) * 8;
+    L.off_shift = static_cast<uint32_t>(off);
+    off += static_cast<size_t>(rows) * 8;
+    L.off_s1 = static_cast<uint32_t>(off);
+    off += static_cast<size_t>(rows) * 8;
+    L.off_s2 = static_cast<uint32_t>(off);
+    off += static_cast<size_t>(rows) * 8;
+    L.off_s3 = static_cast<uint32_t>(off);
+    off += static_cast<size_t>(rows) * 8;
+    L.off_s4 = static_cast<uint32_t>(off);
+    off += static_cast<size_t>(rows) * 8;
+    L.off_cnt = static_cast<uint32_t>(off);
+    off += static_cast<size_t>(P.n_sub) * rows * 4;
+    off = align_up(off, kAlign);
+    if (off > 0x7FFFFFFFull) return fail(PYFPT_EINVAL, "per-workgroup table too large (%zu bytes)", off);
+    L.slice_bytes = static_cast<uint32_t>(off);
+    return PYFPT_OK;
+}
+
+// workspace map
+struct WsMap {
+    size_t queue, inst, order, vbeg, thr, edges, mi, counts, values, slices, total, upload_bytes;
+};
+
+WsMap ws_map(const Prepared &P, int n_wg) {
+    WsMap m{};
+    size_t o = 0;
+    m.queue = o; o += kAlign;
+    m.inst = o; o = align_up(o + P.inst.size() * sizeof(InstDev), kAlign);
+    m.order = o; o = align_up(o + P.order.size() * 4, kAlign);
+    m.vbeg = o; o = align_up(o + P.vbeg_sorted.size() * 8, kAlign);
+    m.thr = o; o = align_up(o + P.thr.size() * 4, kAlign);
+    m.edges = o; o = align_up(o + P.edges.size() * 8, kAlign);
+    m.mi = o; o = align_up(o + P.mi.size() * sizeof(MergeInst), kAlign);
+    m.upload_bytes = o - m.inst;
+    m.counts = o; o = align_up(o + P.counts_total * 8, kAlign);
+    m.values = o; o = align_up(o + P.values_total * 8, kAlign);
+    m.slices = o; o += static_cast<size_t>(n_wg) * P.lay.slice_bytes;
+    m.total = align_up(o, kAlign);
+    return m;
+}
+
+void resolve_cfg(const Device &d, const Prepared &P, LaunchCfg &c, bool &lds) {
+    if (c.block <= 0) c.block = 512;
+    if (c.wg_per_cu <= 0) c.wg_per_cu = 2;
+    if (c.chunk <= 0) c.chunk = 1;
+    // LDS budget per workgroup: the CU's LDS shared by its resident workgroups
+    const size_t budget = std::min<size_t>(d.max_lds, 160 * 1024 / static_cast<size_t>(c.wg_per_cu));
+    lds = P.lay.slice_bytes <= budget;
+}
+
+std::string signature(const Prepared &P, uint64_t seed_unused) {
+    (void)seed_unused;
+    char buf[256];
+    snprintf(buf, sizeof buf, "p%d b%d i%zu r%u j%u v%llu", P.pot, P.bias, P.inst.size(), P.lay.n_rows, P.n_sub,
+             static_cast<unsigned long long>(P.v_total));
+    return buf;
+}
+
+struct RunCtx {
+    Device *d;
+    hipStream_t stream;
+};
+
+int run_prepared(Device &d, const Prepared &P, uint64_t seed, const LaunchCfg &cfg_in, const pyfpt_options *opt,
+                 hipStream_t stream, void *ws, size_t ws_bytes, bool use_graph, float *timing) {
+    LaunchCfg cfg = cfg_in;
+    bool lds = false;
+    resolve_cfg(d, P, cfg, lds);
+    if (cfg.block < 64 || cfg.block > 1024 || cfg.block % 64)
+        return fail(PYFPT_EINVAL, "block must be a multiple of 64 in 64..1024");
+    if (cfg.wg_per_cu * cfg.block > 2048) return fail(PYFPT_EINVAL, "wg_per_cu * block must be <= 2048");
+    const int n_wg = d.cus * cfg.wg_per_cu;
+    const WsMap m = ws_map(P, n_wg);
+    if (ws_bytes < m.total) return fail(PYFPT_ENOMEM, "workspace too small: need %zu bytes, have %zu", m.total, ws_bytes);
+    unsigned char *W = static_cast<unsigned char *>(ws);
+
+    // upload through the pinned staging buffer
+    if (d.pinned_bytes < m.upload_bytes) {
+        if (d.pinned) {
+            HIP_TRY(hipEventSynchronize(d.pinned_done), "hipEventSynchronize");
+            (void)hipHostFree(d.pinned);
+            d.pinned = nullptr;
+        }
+        HIP_TRY(hipHostMalloc(&d.pinned, m.upload_bytes, hipHostMallocDefault), "hipHostMalloc");
+        d.pinned_bytes = m.upload_bytes;
+    } else {
+        HIP_TRY(hipEventSynchronize(d.pinned_done), "hipEventSynchronize");
+    }
+    unsigned char *H = static_cast<unsigned char *>(d.pinned);
+    std::memset(H, 0, m.upload_bytes);
+    std::memcpy(H + (m.inst - m.inst), P.inst.data(), P.inst.size() * sizeof(InstDev));
+    std::memcpy(H + (m.order - m.inst), P.order.data(), P.order.size() * 4);
+    std::memcpy(H + (m.vbeg - m.inst), P.vbeg_sorted.data(), P.vbeg_sorted.size() * 8);
+    std::memcpy(H + (m.thr - m.inst), P.thr.data(), P.thr.size() * 4);
+    std::memcpy(H + (m.edges - m.inst), P.edges.data(), P.edges.size() * 8);
+    std::memcpy(H + (m.mi - m.inst), P.mi.data(), P.mi.size() * sizeof(MergeInst));
+    HIP_TRY(hipMemcpyAsync(W + m.inst, H, m.upload_bytes, hipMemcpyHostToDevice, stream), "upload");
+    HIP_TRY(hipEventRecord(d.pinned_done, stream), "hipEventRecord");
+
+    StepArgs sa{};
+    sa.inst = reinterpret_cast<const InstDev *>(W + m.inst);
+    sa.order = reinterpret_cast<const uint32_t *>(W + m.order);
+    sa.vbeg_sorted = reinterpret_cast<const uint64_t *>(W + m.vbeg);
+    sa.n_inst = static_cast<int32_t>(P.order.size());
+    sa.thr = reinterpret_cast<const uint32_t *>(W + m.thr);
+    sa.queue = reinterpret_cast<unsigned long long *>(W + m.queue);
+    sa.v_total = P.v_total;
+    sa.key0 = static_cast<uint32_t>(seed);
+    sa.key1 = static_cast<uint32_t>(seed >> 32);
+    sa.slices = W + m.slices;
+    sa.lay = P.lay;
+    sa.chunk = static_cast<uint32_t>(cfg.chunk);
+    if (opt && opt->dump.n) {
+        if (!opt->dump.k || !opt->dump.lw || !opt->dump.phi || !opt->dump.status || opt->dump.stride == 0)
+            return fail(PYFPT_EINVAL, "dump: all four arrays and stride >= 1 are required");
+        sa.dump.n = opt->dump.n;
+        sa.dump.stride = opt->dump.stride;
+        sa.dump.k = opt->dump.k;
+        sa.dump.lw = opt->dump.lw;
+        sa.dump.phi = opt->dump.phi;
+        sa.dump.status = opt->dump.status;
+    }
+    MergeArgs ma{};
+    ma.slices = W + m.slices;
+    ma.n_wg = n_wg;
+    ma.lay = P.lay;
+    ma.mi = reinterpret_cast<const MergeInst *>(W + m.mi);
+    ma.n_inst = static_cast<int32_t>(P.mi.size());
+    ma.edges = reinterpret_cast<const double *>(W + m.edges);
+    ma.counts = reinterpret_cast<uint64_t *>(W + m.counts);
+    ma.values = reinterpret_cast<double *>(W + m.values);
+    const size_t lds_bytes = lds ? P.lay.slice_bytes : 0;
+
+    auto enqueue = [&](bool timed) -> int {
+        HIP_TRY(launch_init_queue(sa.queue, stream), "launch init");
+        if (timed) HIP_TRY(hipEventRecord(d.ev[0], stream), "event");
+        HIP_TRY(launch_step(P.pot, P.bias, lds, n_wg, cfg.block, lds_bytes, sa, stream), "launch step kernel");
+        if (timed) HIP_TRY(hipEventRecord(d.ev[1], stream), "event");
+        HIP_TRY(launch_merge(ma, static_cast<int>(P.lay.n_rows), static_cast<int>(P.n_sub), stream), "launch merge");
+        if (timed) HIP_TRY(hipEventRecord(d.ev[2], stream), "event");
+        return PYFPT_OK;
+    };
+
+    if (use_graph && !timing) {
+        // key: everything the recorded launches depend on
+        std::vector<unsigned char> key;
+        auto put = [&](const void *p, size_t n) {
+            const unsigned char *c = static_cast<const unsigned char *>(p);
+            key.insert(key.end(), c, c + n);
+        };
+        put(&sa, sizeof sa);
+        put(&ma, sizeof ma);
+        put(&cfg, sizeof cfg);
+        put(&lds, sizeof lds);
+        int pb[2] = {P.pot, P.bias};
+        put(pb, sizeof pb);
+        put(&stream, sizeof stream);
+        if (!d.gexec || key != d.gkey) {
+            if (d.gexec) { (void)hipGraphExecDestroy(d.gexec); d.gexec = nullptr; }
+            if (d.graph) { (void)hipGraphDestroy(d.graph); d.graph = nullptr; }
+            HIP_TRY(hipStreamBeginCapture(stream, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+            int rc = enqueue(false);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(stream, &g);
+            if (rc) return rc;
+            if (e != hipSuccess) return dev_fail(e, "hipStreamEndCapture");
+            d.graph = g;
+            HIP_TRY(hipGraphInstantiate(&d.gexec, d.graph, nullptr, nullptr, 0), "hipGraphInstantiate");
+            d.gkey = key;
+        }
+        HIP_TRY(hipGraphLaunch(d.gexec, stream), "hipGraphLaunch");
+    } else {
+        int rc = enqueue(timing != nullptr);
+        if (rc) return rc;
+    }
+    if (timing) {
+        HIP_TRY(hipEventSynchronize(d.ev[2]), "hipEventSynchronize");
+        HIP_TRY(hipEventElapsedTime(&timing[0], d.ev[0], d.ev[1]), "hipEventElapsedTime");
+        HIP_TRY(hipEventElapsedTime(&timing[1], d.ev[1], d.ev[2]), "hipEventElapsedTime");
+    }
+    return PYFPT_OK;
+}
+
+int copy_out(const Prepared &P, void *ws, int n_wg, pyfpt_result *out, hipStream_t stream) {
+    const WsMap m = ws_map(P, n_wg);
+    unsigned char *W = static_cast<unsigned char *>(ws);
+    bool host = false;
+    for (size_t i = 0; i < P.inst.size(); ++i) {
+        if (!out[i].counts || !out[i].values) return fail(PYFPT_EINVAL, "result %zu: NULL buffer", i);
+        const hipMemcpyKind kind = out[i].on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+        host |= !out[i].on_device;
+        HIP_TRY(hipMemcpyAsync(out[i].counts, W + m.counts + P.mi[i].counts_off * 8, P.rl[i].n_counts * 8, kind, stream),
+                "copy counts");
+        HIP_TRY(hipMemcpyAsync(out[i].values, W + m.values + P.mi[i].values_off * 8, P.rl[i].n_values * 8, kind, stream),
+                "copy values");
+    }
+    if (host) HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    return PYFPT_OK;
+}
+
+int ensure_ws(Device &d, size_t bytes, void **ws) {
+    if (d.ws_bytes < bytes) {
+        if (d.ws) {
+            HIP_TRY(hipDeviceSynchronize(), "hipDeviceSynchronize");
+            (void)hipFree(d.ws);
+            d.ws = nullptr;
+            d.ws_bytes = 0;
+            if (d.gexec) { (void)hipGraphExecDestroy(d.gexec); d.gexec = nullptr; }
+            if (d.graph) { (void)hipGraphDestroy(d.graph); d.graph = nullptr; }
+        }
+        hipError_t e = hipMalloc(&d.ws, bytes);
+        if (e != hipSuccess) return fail(PYFPT_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+        d.ws_bytes = bytes;
+    }
+    *ws = d.ws;
+    return PYFPT_OK;
+}
+
+// Measured autotuning of (block, wg_per_cu, chunk): short runs of the same
+// instances with fewer trajectories, scored by trajectory-steps per second.
+int autotune(Device &d, const pyfpt_instance *ins, int n_inst, uint64_t seed, hipStream_t stream,
+             const Prepared &P, LaunchCfg &best) {
+    const std::string key = signature(P, seed);
+    auto it = d.tuned.find(key);
+    if (it != d.tuned.end()) {
+        best = it->second;
+        return PYFPT_OK;
+    }
+    static const LaunchCfg cands[] = {
+        {256, 4, 1}, {512, 2, 1}, {1024, 1, 1}, {256, 8, 1}, {512, 2, 4},
+    };
+    // about one trajectory per lane of the largest grid, split over instances by their share
+    const double lanes = static_cast<double>(d.cus) * 2048.0;
+    const double total = static_cast<double>(P.v_total);
+    std::vector<pyfpt_instance> cal(ins, ins + n_inst);
+    for (int i = 0; i < n_inst; ++i) {
+        const double share = total > 0 ? static_cast<double>(ins[i].n_traj) / total : 0.0;
+        cal[i].n_traj = std::min<uint64_t>(ins[i].n_traj, static_cast<uint64_t>(std::ceil(lanes * share)));
+    }
+    Prepared C;
+    int rc = prepare(cal.data(), n_inst, C);
+    if (rc) return rc;
+    double best_rate = -1;
+    best = LaunchCfg{512, 2, 1};
+    std::vector<uint64_t> counts(C.counts_total);
+    for (const LaunchCfg &c : cands) {
+        LaunchCfg cc = c;
+        bool lds = false;
+        resolve_cfg(d, C, cc, lds);
+        const int n_wg = d.cus * cc.wg_per_cu;
+        const WsMap m = ws_map(C, n_wg);
+        void *ws = nullptr;
+        if ((rc = ensure_ws(d, m.total, &ws))) return rc;
+        float tm[2] = {0, 0};
+        if ((rc = run_prepared(d, C, seed ^ 0x5DEECE66Dull, cc, nullptr, stream, ws, d.ws_bytes, false, tm))) return rc;
+        HIP_TRY(hipMemcpyAsync(counts.data(), static_cast<unsigned char *>(ws) + m.counts, C.counts_total * 8,
+                               hipMemcpyDeviceToHost, stream), "tune copy");
+        HIP_TRY(hipStreamSynchronize(stream), "tune sync");
+        double steps = 0;
+        for (size_t i = 0; i < C.inst.size(); ++i) steps += static_cast<double>(counts[C.mi[i].counts_off + C.rl[i].total_steps]);
+        const double rate = steps / std::max(1e-6, static_cast<double>(tm[0]));
+        if (rate > best_rate) {
+            best_rate = rate;
+            best = c;
+        }
+    }
+    d.tuned[key] = best;
+    return PYFPT_OK;
+}
+
+int run_batch_impl(const pyfpt_instance *ins, int n_inst, uint64_t seed, pyfpt_result *out, const pyfpt_options *opt) {
+    if (!ins || !out) return fail(PYFPT_EINVAL, "NULL instance or result array");
+    Prepared P;
+    int rc = prepare(ins, n_inst, P);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lock(g_mu);
+    Device *d = nullptr;
+    if ((rc = get_device(&d))) return rc;
+    if (d->cus <= 0) return fail(PYFPT_EDEVICE, "no compute units reported");
+    hipStream_t stream = opt ? static_cast<hipStream_t>(opt->stream) : nullptr;
+    LaunchCfg cfg;
+    if (opt) {
+        cfg.block = opt->block;
+        cfg.wg_per_cu = opt->wg_per_cu;
+        cfg.chunk = opt->chunk;
+    }
+    if ((cfg.block <= 0 || cfg.wg_per_cu <= 0 || cfg.chunk <= 0) && P.v_total > 0) {
+        LaunchCfg t;
+        if ((rc = autotune(*d, ins, n_inst, seed, stream, P, t))) return rc;
+        if (cfg.block <= 0) cfg.block = t.block;
+        if (cfg.wg_per_cu <= 0) cfg.wg_per_cu = t.wg_per_cu;
+        if (cfg.chunk <= 0) cfg.chunk = t.chunk;
+    }
+    LaunchCfg rcfg = cfg;
+    bool lds;
+    resolve_cfg(*d, P, rcfg, lds);
+    const int n_wg = d->cus * rcfg.wg_per_cu;
+    const WsMap m = ws_map(P, n_wg);
+    void *ws = nullptr;
+    size_t ws_bytes = 0;
+    if (opt && opt->workspace) {
+        ws = opt->workspace;
+        ws_bytes = opt->workspace_bytes;
+    } else {
+        if ((rc = ensure_ws(*d, m.total, &ws))) return rc;
+        ws_bytes = d->ws_bytes;
+    }
+    const bool graph = opt && opt->use_graph;
+    if (graph && stream == nullptr) return fail(PYFPT_EINVAL, "use_graph needs a non-null stream (the null stream cannot be captured)");
+    if ((rc = run_prepared(*d, P, seed, rcfg, opt, stream, ws, ws_bytes, graph, opt ? opt->timing_ms : nullptr))) return rc;
+    return copy_out(P, ws, n_wg, out, stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+int pyfpt_result_layout(int32_t n_bins, int32_t n_sub, pyfpt_layout *out) {
+    if (!out) return fail(PYFPT_EINVAL, "NULL layout");
+    if (n_bins < 1) return fail(PYFPT_EINVAL, "n_bins must be >= 1");
+    if (n_sub == 0) n_sub = kDefaultNsub;
+    if (n_sub < 2 || n_sub > 64) return fail(PYFPT_EINVAL, "n_sub must be 0 or 2..64");
+    const ResultLayout L = result_layout(static_cast<uint32_t>(n_bins), static_cast<uint32_t>(n_sub));
+    out->n_counts = L.n_counts;
+    out->n_values = L.n_values;
+    out->count = L.count;
+    out->jk_count = L.jk_count;
+    out->n_traj = L.n_traj;
+    out->total_steps = L.total_steps;
+    out->lse_w = L.lse_w;
+    out->lse_w2 = L.lse_w2;
+    out->jk_lse_w = L.jk_lse_w;
+    out->mean_lnw = L.mean_lnw;
+    out->m2_lnw = L.m2_lnw;
+    out->m3_lnw = L.m3_lnw;
+    out->m4_lnw = L.m4_lnw;
+    out->log_p = L.log_p;
+    out->rel_err_jk = L.rel_err_jk;
+    out->rel_err_kish = L.rel_err_kish;
+    out->lse_w_all = L.lse_w_all;
+    out->lse_w2_all = L.lse_w2_all;
+    out->lse_wk = L.lse_wk;
+    out->lse_wk2 = L.lse_wk2;
+    out->sum_k2 = L.sum_k2;
+    return PYFPT_OK;
+}
+
+int pyfpt_run_batch(const pyfpt_instance *inst, int32_t n_inst, uint64_t seed, pyfpt_result *out,
+                    const pyfpt_options *opt) {
+    try {
+        return run_batch_impl(inst, n_inst, seed, out, opt);
+    } catch (...) {
+        return fail(PYFPT_ENOMEM, "host exception (allocation failure)");
+    }
+}
+
+int pyfpt_run(const pyfpt_potential *pot, double phi_in, double phi_end, double phi_uv, double dN,
+              const pyfpt_bias *bias, uint64_t n_traj, uint64_t seed, const pyfpt_bins *bins, pyfpt_result *out,
+              const pyfpt_options *opt) {
+    if (!pot || !bias || !bins || !out) return fail(PYFPT_EINVAL, "NULL argument");
+    pyfpt_instance I;
+    std::memset(&I, 0, sizeof I);
+    I.pot = *pot;
+    I.bias = *bias;
+    I.phi_in = phi_in;
+    I.phi_end = phi_end;
+    I.phi_uv = phi_uv;
+    I.dN = dN;
+    I.n_traj = n_traj;
+    I.bins = *bins;
+    if (opt) {
+        I.k_max = opt->k_max;
+        I.phi_esc = opt->phi_esc;
+        I.stream = opt->stream_id;
+    }
+    return pyfpt_run_batch(&I, 1, seed, out, opt);
+}
+
+int pyfpt_workspace_size(const pyfpt_instance *inst, int32_t n_inst, const pyfpt_options *opt, size_t *bytes) {
+    if (!inst || !bytes) return fail(PYFPT_EINVAL, "NULL argument");
+    try {
+        Prepared P;
+        int rc = prepare(inst, n_inst, P);
+        if (rc) return rc;
+        std::lock_guard<std::mutex> lock(g_mu);
+        Device *d = nullptr;
+        if ((rc = get_device(&d))) return rc;
+        LaunchCfg c;
+        if (opt) {
+            c.block = opt->block;
+            c.wg_per_cu = opt->wg_per_cu;
+            c.chunk = opt->chunk;
+        }
+        if (c.wg_per_cu <= 0) c.wg_per_cu = 8;   // the largest grid the autotuner may pick
+        bool lds;
+        resolve_cfg(*d, P, c, lds);
+        *bytes = ws_map(P, d->cus * c.wg_per_cu).total;
+        return PYFPT_OK;
+    } catch (...) {
+        return fail(PYFPT_ENOMEM, "host exception (allocation failure)");
+    }
+}
+
+int pyfpt_device_cus(int32_t *cus) {
+    if (!cus) return fail(PYFPT_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lock(g_mu);
+    Device *d = nullptr;
+    int rc = get_device(&d);
+    if (rc) {
+        *cus = 0;
+        return rc;
+    }
+    *cus = d->cus;
+    return PYFPT_OK;
+}
+
+const char *pyfpt_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,78 @@
+"""Shared test helpers: instance -> oracle model, and result comparisons."""
+import math
+
+import numpy as np
+
+import oracle as O
+
+
+def to_model(inst) -> O.Model:
+    return O.Model.from_instance(inst)
+
+
+def close_lse(a, b, rel=1e-12):
+    """Log-sums agree: both -inf, or |a - b| <= rel * max(1, |b|)."""
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    both_inf = np.isneginf(a) & np.isneginf(b)
+    with np.errstate(invalid="ignore"):
+        ok = both_inf | (np.abs(a - b) <= rel * np.maximum(1.0, np.abs(b)))
+    return bool(np.all(ok)), np.nonzero(~ok)[0]
+
+
+def assert_histogram_matches(res, h, rel=1e-12):
+    """GPU result vs the oracle's plain-definition histogram of the same runs."""
+    B = res.n_bins
+    assert np.array_equal(res.count.astype(np.int64), h.count), (res.count, h.count)
+    assert np.array_equal(res.jk_count.astype(np.int64), h.jk_count)
+    if h.n_traj == 0:
+        assert np.all(np.isneginf(res.lse_w)) and np.all(np.isneginf(res.jk_lse_w))
+        assert res.total_steps == 0 and res.n_traj == 0
+        return
+    ok, bad = close_lse(res.lse_w, h.lse_w, rel)
+    assert ok, ("lse_w", bad, res.lse_w[bad], h.lse_w[bad])
+    ok, bad = close_lse(res.lse_w2, h.lse_w2, rel)
+    assert ok, ("lse_w2", bad)
+    ok, bad = close_lse(res.jk_lse_w, h.jk_lse_w, rel)
+    assert ok, ("jk_lse_w", bad)
+    assert res.total_steps == h.total_steps
+    assert res.n_traj == h.n_traj
+    for name in ("lse_w_all", "lse_w2_all", "lse_wk", "lse_wk2"):
+        ok, _ = close_lse([getattr(res, name)], [getattr(h, name)], rel)
+        assert ok, (name, getattr(res, name), getattr(h, name))
+    assert abs(res.sum_k2 - h.sum_k2) <= 1e-12 * h.sum_k2
+    # moments of ln w per row (population central moments)
+    nz = h.count > 0
+    assert np.all(np.isnan(res.mean_lnw[~nz]))
+    sd = np.sqrt(np.maximum(h.m2_lnw[nz], 0))
+    scale = np.maximum(1.0, np.abs(h.mean_lnw[nz]))
+    assert np.all(np.abs(res.mean_lnw[nz] - h.mean_lnw[nz]) <= 1e-9 * scale)
+    assert np.all(np.abs(res.m2_lnw[nz] - h.m2_lnw[nz]) <= 1e-9 * scale ** 2 + 1e-9 * h.m2_lnw[nz])
+    assert np.all(np.abs(res.m3_lnw[nz] - h.m3_lnw[nz]) <= 1e-7 * (sd + 1e-3 * scale) ** 3 + 1e-12)
+    assert np.all(np.abs(res.m4_lnw[nz] - h.m4_lnw[nz]) <= 1e-7 * (sd + 1e-3 * scale) ** 4 + 1e-12)
+    # estimators
+    lp = h.log_p_naive()
+    fin = np.isfinite(lp)
+    assert np.array_equal(np.isfinite(res.log_p), fin)
+    assert np.all(np.abs(res.log_p[fin] - lp[fin]) <= rel * np.maximum(1, np.abs(lp[fin])))
+    jk = h.jackknife_rel_err()
+    f2 = np.isfinite(jk) & fin
+    assert np.all(np.abs(res.rel_err_jk[f2] - jk[f2]) <= 1e-8 * np.maximum(1e-3, jk[f2]))
+    kish = np.sqrt(np.maximum(h.kish_rel_err2(), 0))
+    f3 = np.isfinite(kish) & (h.count[:B] > 0)
+    assert np.all(np.abs(res.rel_err_kish[f3] - kish[f3]) <= 1e-8 * np.maximum(1e-3, kish[f3]) + 1e-7)
+
+
+def assert_dump_matches(dump, tr):
+    """Per-trajectory parity: identical step count, status, final field (bit for bit)
+    and log-weight (bit for bit: both accumulate the same binary32 increments in order)."""
+    n = len(tr.k)
+    k = dump.k[:n].astype(np.uint64)
+    bad = np.nonzero(k != tr.k)[0]
+    assert bad.size == 0, ("k differs", bad[:10], k[bad[:10]], tr.k[bad[:10]])
+    assert np.array_equal(dump.status[:n], tr.status)
+    assert np.array_equal(dump.phi[:n].astype(np.float32).view(np.uint32),
+                          tr.phi.astype(np.float32).view(np.uint32))
+    lw_ok = np.abs(dump.lw[:n] - tr.lw) <= 1e-5 * np.maximum(1.0, np.abs(tr.lw))
+    assert np.all(lw_ok), ("lw beyond 1e-5", np.nonzero(~lw_ok)[0][:10])
+    assert np.array_equal(dump.lw[:n], tr.lw), "lw not bit-identical"

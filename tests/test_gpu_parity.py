@@ -1,0 +1,183 @@
+"""GPU parity: the HIP path against the CPU oracle on the same seeded inputs.
+
+Bar: identical step counts, statuses, final fields and log-weights for every
+dumped run (the step count is decided in binary32 on both sides); identical
+counts per row and per jackknife subset; binary64 log-sums within 1e-12
+relative (only the summation order differs); log-weights within the
+1e-5 relative tolerance a fortiori.
+"""
+import math
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+from helpers import assert_dump_matches, assert_histogram_matches, to_model
+
+pytestmark = pytest.mark.gpu
+
+SEED = 0
+CFG = dict(block=512, wg_per_cu=2, chunk=1)
+
+
+@pytest.fixture(scope="module")
+def fpt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2206_11234_amd as F
+    return F
+
+
+def _oracle(inst, n=None, stride=1):
+    n = inst.n_traj if n is None else n
+    tr = O.simulate(to_model(inst), SEED, n, t0=0, stride=stride)
+    return tr
+
+
+def _print_case(label, **kw):
+    print(f"[case] {label} {kw}", flush=True)
+
+
+def test_c1_bit_exact_every_run(fpt):
+    """Config C1 in full: 1e4 direct-sampling runs, every run compared."""
+    inst = W.c1()
+    _print_case("C1", n=inst.n_traj)
+    res, dump, _ = fpt.run(inst, SEED, dump_n=inst.n_traj, dump_stride=1, **CFG)
+    tr = _oracle(inst)
+    assert_dump_matches(dump, tr)
+    h = O.histogram(tr, inst.dN, inst.edges)
+    assert_histogram_matches(res, h)
+    assert np.all(dump.lw == 0.0)
+
+
+def test_c2_batch_prefix_bit_exact(fpt):
+    """All six C2 instances (drift- and diffusion-dominated, A = 1, 2, 4) in one batched launch,
+    on the first ids of each; every run compared and the histograms of those runs."""
+    sizes = [1536, 1536, 1536, 700, 300, 300]
+    insts = [W.with_runs(i, n) for i, n in zip(W.c2(), sizes)]
+    _print_case("C2 prefix batch", sizes=sizes)
+    results, dumps, _ = fpt.run_batch(insts, SEED, dump_n=max(sizes), dump_stride=1, **CFG)
+    for inst, res, dump in zip(insts, results, dumps):
+        tr = _oracle(inst)
+        assert_dump_matches(dump, tr)
+        h = O.histogram(tr, inst.dN, inst.edges)
+        assert_histogram_matches(res, h)
+
+
+@pytest.mark.parametrize("block,wg,chunk", [(64, 8, 1), (256, 4, 4), (1024, 1, 1), (512, 2, 16)])
+def test_launch_shape_does_not_change_results(fpt, block, wg, chunk):
+    """Counter-based noise: every run's path depends only on (seed, stream, t), so counts are
+    identical for any workgroup size, grid and queue claim chunk; ragged n_traj."""
+    inst = W.with_runs(W.c2()[3], 1237)
+    _print_case("shape", block=block, wg=wg, chunk=chunk)
+    res, dump, _ = fpt.run(inst, SEED, block=block, wg_per_cu=wg, chunk=chunk, dump_n=1237)
+    tr = _oracle(inst)
+    assert_dump_matches(dump, tr)
+    assert_histogram_matches(res, O.histogram(tr, inst.dN, inst.edges))
+
+
+def test_edge_cases(fpt):
+    """Empty run, one run, a cap that censors every run mid-group, a start on the wall,
+    escapes, the flat potential, the bump potential and the power-law bias."""
+    base = W.c2()[3]
+    cases = {
+        "empty": W.with_runs(base, 0),
+        "one": W.with_runs(base, 1),
+        "all_censored": W.Instance("cens", m=1.0, phi_in=6.0, phi_uv=8.0, bias=W.BIAS_NOISE_SCALED, A=1.0,
+                                   dN=1e-3, n_traj=333, k_max=7, edges=np.linspace(0, 0.1, 11)),
+        "start_on_wall": W.Instance("wall", m=1.0, phi_in=math.sqrt(42), phi_uv=math.sqrt(42),
+                                    bias=W.BIAS_NOISE_SCALED, A=0.4, dN=1e-3, n_traj=200,
+                                    edges=np.geomspace(0.5, 60, 41)),
+        "escape": W.Instance("esc", m=1.0, phi_in=3.0, bias=W.BIAS_NOISE_SCALED, A=4.0, dN=1e-3, n_traj=300,
+                             phi_esc=4.0, edges=np.linspace(0, 5, 21)),
+        "flat": W.Instance("flat", pot=W.POT_FLAT, V0=3 * (2 * math.pi) ** 2, phi_in=1.0, phi_end=0.0,
+                           phi_uv=1.5, dN=1e-3, n_traj=500, edges=np.linspace(0, 8, 41)),
+        "flat_levy_bias": W.Instance("levy", pot=W.POT_FLAT, V0=3 * (2 * math.pi) ** 2, phi_in=1.0, phi_end=0.0,
+                                     phi_esc=5.0, bias=W.BIAS_NOISE_SCALED, A=-30.0, dN=1e-5, n_traj=500,
+                                     edges=np.linspace(0.015, 0.06, 31)),
+        "bump": W.with_runs(W.c5(), 64),
+        "power": W.Instance("pow", m=0.01, phi_in=5.0, bias=W.BIAS_POWER, A=2e-5, p=3, dN=1e-3, n_traj=400,
+                            edges=np.linspace(5.6, 6.0, 41)),
+    }
+    for name, inst in cases.items():
+        _print_case("edge", name=name, n=inst.n_traj)
+        res, dump, _ = fpt.run(inst, SEED, dump_n=max(1, inst.n_traj), block=256, wg_per_cu=2, chunk=1)
+        tr = _oracle(inst)
+        if inst.n_traj:
+            assert_dump_matches(dump, tr)
+        assert_histogram_matches(res, O.histogram(tr, inst.dN, inst.edges))
+        if name == "all_censored":
+            assert res.count[-2] == inst.n_traj and res.total_steps == 7 * inst.n_traj
+        if name == "escape":
+            assert res.count[-1] > 0
+
+
+def test_single_entry_point_matches_batch(fpt):
+    inst = W.with_runs(W.c2()[0], 2000)
+    a = fpt.run_single_abi(inst, SEED)
+    b, _, _ = fpt.run(inst, SEED, **CFG)
+    assert np.array_equal(a.count, b.count)
+    assert np.array_equal(a.jk_count, b.jk_count)
+    assert a.total_steps == b.total_steps
+
+
+def test_graph_replays_match_eager(fpt):
+    """hipGraph capture of the launch sequence: several replays with eager work and
+    synchronisations between them, each identical in counts to the eager run."""
+    import torch
+    inst = W.with_runs(W.c2()[0], 3000)
+    eager, _, _ = fpt.run(inst, SEED, block=256, wg_per_cu=4, chunk=1)
+    side = torch.cuda.Stream()
+    for rep in range(3):
+        with torch.cuda.stream(side):
+            g, _, _ = fpt.run(inst, SEED, block=256, wg_per_cu=4, chunk=1, use_graph=True)
+        x = torch.randn(1000, device="cuda").sum()
+        torch.cuda.synchronize()
+        assert np.array_equal(g.count, eager.count), rep
+        assert np.array_equal(g.jk_count, eager.jk_count), rep
+        assert g.total_steps == eager.total_steps
+
+
+def test_full_size_c2_sampled_runs(fpt):
+    """C2 at its full size (6 x 1e6 runs) in the benchmark's launch: a sample of runs (every
+    65536th id of each instance) is recomputed one by one by the oracle and must match bit for
+    bit; the totals obey what holds at any size (every launched run lands in one row, the weight
+    average is one within its error)."""
+    insts = W.c2()
+    stride = 65536
+    n_dump = (insts[0].n_traj + stride - 1) // stride
+    _print_case("C2 full", stride=stride)
+    results, dumps, _ = fpt.run_batch(insts, SEED, dump_n=n_dump, dump_stride=stride, **CFG)
+    for inst, res, dump in zip(insts, results, dumps):
+        assert int(res.count.sum()) == inst.n_traj
+        tr = O.simulate(to_model(inst), SEED, n_dump, t0=0, stride=stride)
+        assert_dump_matches(dump, tr)
+        mean_w = math.exp(res.lse_w_all) / inst.n_traj
+        ess = math.exp(2 * res.lse_w_all - res.lse_w2_all)
+        if res.count[-2] == 0:
+            assert abs(mean_w - 1) < 6 / math.sqrt(ess) + 1e-3, (inst.name, mean_w, ess)
+
+
+def test_autotuned_launch_matches(fpt):
+    """The autotuner only picks the launch shape: results equal the fixed-shape run."""
+    inst = W.with_runs(W.c2()[1], 4000)
+    a, _, _ = fpt.run(inst, SEED)
+    b, _, _ = fpt.run(inst, SEED, **CFG)
+    assert np.array_equal(a.count, b.count)
+    assert np.array_equal(a.jk_count, b.jk_count)
+    assert a.total_steps == b.total_steps
+
+
+def test_mixed_none_and_noise_scaled_batch(fpt):
+    """No bias and the noise-scaled bias share one launch (no bias = A 0): each instance's runs
+    are bit-identical to the oracle's."""
+    insts = [W.with_runs(W.c1(), 1500), W.with_runs(W.c2()[3], 300)]
+    results, dumps, _ = fpt.run_batch(insts, SEED, dump_n=1500, **CFG)
+    for inst, res, dump in zip(insts, results, dumps):
+        tr = _oracle(inst)
+        assert_dump_matches(dump, tr)
+        assert_histogram_matches(res, O.histogram(tr, inst.dN, inst.edges))
