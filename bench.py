@@ -22,13 +22,20 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz
-# (the 157.3 TFLOP/s fp32 vector peak counts packed FMAs: 4 flops per lane-op).
-PEAK_LANE_OPS = 256 * 4 * 16 * 2.4e9
-# Algorithmic lane operations per trajectory-step of the quadratic, noise-scaled path
-# (each IEEE operation, division and square root included, and each integer operation
-# of the noise counts once):  step 21 + Philox 80/4 + uniforms 16/4 + Box-Muller 46/2.
-OPS_PER_STEP = 21 + 20 + 4 + 23
+# VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 32 lanes per clock x 2.4 GHz = 7.86e13
+# lane-ops/s, i.e. the 157.3 TFLOP/s fp32 vector peak divided by 2 flops per FMA.  Measured on
+# the chip: 32-bit add/mul/logic/move issue at 32 lanes per clock per SIMD, fma, 32x32 integer
+# multiplies, f64 add and conversions at 16 (they occupy two issue slots).
+PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
+# Algorithmic lane operations per trajectory-step of the quadratic, noise-scaled path: every
+# binary32/binary64/integer operation of the step semantics counts once (fma = 1):
+#   step 31 (Newton reciprocal 7, drift/noise/bias 6, EM update 3, weight 6, wall 3, k 1, status 6)
+#   Philox 60/4 (two 32x32->64 multiplies and four xors per round, ten rounds per 4 steps)
+#   uniforms 20/4, Box-Muller 72/2 (log 29, -2L 1, sqrt 13, sincos 27, rho*cos/sin 2).
+OPS_PER_STEP = 31 + 15 + 5 + 36
+# HBM bytes per launch of the step kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE (see profiles/),
+# None until taken on the current kernel
+TRAFFIC = None
 
 
 def parse():
@@ -39,9 +46,12 @@ def parse():
     p.add_argument("--n-traj", type=int, default=1_000_000)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     p.add_argument("--cpu-seconds", type=float, default=15.0)
-    p.add_argument("--block", type=int, default=0)
-    p.add_argument("--wg-per-cu", type=int, default=0)
-    p.add_argument("--chunk", type=int, default=0)
+    # fixed launch shape (a sweep on MI355X put every shape from 64x16 to 1024x1 within 2%);
+    # --autotune lets the library's measured autotuner pick it instead
+    p.add_argument("--block", type=int, default=512)
+    p.add_argument("--wg-per-cu", type=int, default=2)
+    p.add_argument("--chunk", type=int, default=1)
+    p.add_argument("--autotune", action="store_true")
     return p.parse_args()
 
 
@@ -88,6 +98,8 @@ def main():
     torch.cuda.set_device(0)
     insts = W.c2(args.n_traj)
     kw = dict(block=args.block, wg_per_cu=args.wg_per_cu, chunk=args.chunk)
+    if args.autotune:
+        kw = dict(block=0, wg_per_cu=0, chunk=0)
     for _ in range(args.warmup):
         F.run_batch(insts, 0, **kw)
     torch.cuda.synchronize()
@@ -129,7 +141,7 @@ def main():
                    "steps_per_pass": steps_per_pass},
         "ess_per_s": ess_total / wall,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                     "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": None,
+                     "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": TRAFFIC,
                      "kernel": "fpt_step_kernel", "kernel_ms": kmean * 1e3,
                      "ops_per_step": OPS_PER_STEP},
     }

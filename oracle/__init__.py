@@ -77,6 +77,8 @@ def lib():
         L.oracle_exp_f32.restype = ctypes.c_float
         L.oracle_log_f32_batch.argtypes = [f32p, f32p, ctypes.c_int64]
         L.oracle_exp_f32_batch.argtypes = [f32p, f32p, ctypes.c_int64]
+        L.oracle_recip_f32_batch.argtypes = [f32p, f32p, ctypes.c_int64]
+        L.oracle_sqrt_f32_batch.argtypes = [f32p, f32p, ctypes.c_int64]
         L.oracle_sincos2pi_f32_batch.argtypes = [f32p, f32p, f32p, ctypes.c_int64]
         L.oracle_normals_f32_batch.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
                                                ctypes.c_uint32, ctypes.c_uint32, f32p]
@@ -189,6 +191,20 @@ def log_f32(x: np.ndarray) -> np.ndarray:
     x = np.ascontiguousarray(x, np.float32)
     y = np.empty_like(x)
     lib().oracle_log_f32_batch(_ptr(x, ctypes.c_float), _ptr(y, ctypes.c_float), x.size)
+    return y
+
+
+def recip_f32(x: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(x, np.float32)
+    y = np.empty_like(x)
+    lib().oracle_recip_f32_batch(_ptr(x, ctypes.c_float), _ptr(y, ctypes.c_float), x.size)
+    return y
+
+
+def sqrt_f32(x: np.ndarray) -> np.ndarray:
+    x = np.ascontiguousarray(x, np.float32)
+    y = np.empty_like(x)
+    lib().oracle_sqrt_f32_batch(_ptr(x, ctypes.c_float), _ptr(y, ctypes.c_float), x.size)
     return y
 
 

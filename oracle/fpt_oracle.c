@@ -37,8 +37,9 @@
  *   MODE_F32 -- every step in IEEE binary32, written operation by operation
  *               with explicit fmaf, no contraction (build with
  *               -ffp-contract=off), with the transcendental functions of the
- *               normal transform written out below (so that the integer step
- *               count is decided in binary32);
+ *               normal transform, the reciprocal and the square root written
+ *               out below as fma sequences (so that the integer step count is
+ *               decided in binary32 by a fixed sequence of operations);
  *   MODE_F64 -- the same semantics in binary64 with libm transcendentals,
  *               used to state the binary32 error of every result.
  *
@@ -98,8 +99,44 @@ static float bits_to_f32(uint32_t b) { float f; memcpy(&f, &b, 4); return f; }
 static uint32_t f32_to_bits(float f) { uint32_t b; memcpy(&b, &f, 4); return b; }
 
 /* ------------------------------------------------------------------ */
+/* binary32 reciprocal of a positive normal x: Newton-Raphson           */
+/* y <- y (2 - x y), written y <- fma(y, fma(-x, y, 1), y), three times */
+/* from the exponent-negating seed bits(0x7EF311C3 - bits(x)) (relative */
+/* error below 5.1%, so 3 steps reach the binary32 rounding level).     */
+/* ------------------------------------------------------------------ */
+float oracle_recip_f32(float x)
+{
+    float y = bits_to_f32(0x7EF311C3u - f32_to_bits(x));
+    for (int i = 0; i < 3; ++i) {
+        float e = fmaf(-x, y, 1.0f);
+        y = fmaf(y, e, y);
+    }
+    return y;
+}
+
+/* ------------------------------------------------------------------ */
+/* binary32 square root of a positive normal x: reciprocal square root  */
+/* by Newton-Raphson y <- y (3 - x y^2)/2, written                      */
+/* y <- fma(y, fma(-x/2, y*y, 1/2), y), three times from the seed       */
+/* bits(0x5F3759DF - (bits(x) >> 1)) (relative error below 3.5%), then  */
+/* sqrt x = x y.                                                        */
+/* ------------------------------------------------------------------ */
+float oracle_sqrt_f32(float x)
+{
+    float y = bits_to_f32(0x5F3759DFu - (f32_to_bits(x) >> 1));
+    float hx = 0.5f * x;
+    for (int i = 0; i < 3; ++i) {
+        float yy = y * y;
+        float e = fmaf(-hx, yy, 0.5f);
+        y = fmaf(y, e, y);
+    }
+    return x * y;
+}
+
+/* ------------------------------------------------------------------ */
 /* binary32 natural logarithm for positive normal inputs.               */
-/* Method: x = 2^e f with f in [sqrt(1/2), sqrt(2)); s = (f-1)/(f+1);   */
+/* Method: x = 2^e f with f in [sqrt(1/2), sqrt(2)); s = (f-1)/(f+1)    */
+/* (the quotient as (f-1) * recip(f+1));                                 */
 /* ln f = 2 atanh(s) = 2 (s + s^3/3 + s^5/5 + s^7/7 + s^9/9 + ...);     */
 /* ln x = e ln2 + ln f with ln2 split in a 16-bit head and a tail.      */
 /* |s| <= 0.1716, so the first omitted term is below 1e-9 relative.    */
@@ -113,7 +150,7 @@ float oracle_log_f32(float x)
         f = bits_to_f32((b & 0x007FFFFFu) | 0x3F000000u);     /* f/2, exact */
         e += 1;
     }
-    float s = (f - 1.0f) / (f + 1.0f);
+    float s = (f - 1.0f) * oracle_recip_f32(f + 1.0f);
     float z = s * s;
     float p = 1.0f / 9.0f;
     p = fmaf(p, z, 1.0f / 7.0f);
@@ -212,7 +249,7 @@ void oracle_normals_f32(uint64_t seed, uint32_t stream, uint64_t t, uint32_t j, 
         float ua = oracle_uniform24(x[2 * pair]);
         float ub = oracle_uniform24(x[2 * pair + 1]);
         float L = oracle_log_f32(ua);
-        float rho = sqrtf(-2.0f * L);
+        float rho = oracle_sqrt_f32(-2.0f * L);
         float c, s;
         oracle_sincos2pi_f32(ub, &c, &s);
         out[2 * pair] = rho * c;
@@ -294,7 +331,8 @@ static void make_consts_f32(const oracle_params *P, consts_f32 *c)
 static void drift_noise_f32(const oracle_params *P, const consts_f32 *c, float phi, float *D, float *S)
 {
     if (P->pot_kind == POT_QUADRATIC) {
-        float d = 2.0f / phi;
+        float y = oracle_recip_f32(phi);
+        float d = y + y;               /* 2/phi */
         *D = -d;
         *S = c->cm * phi;
     } else if (P->pot_kind == POT_QUADRATIC_BUMP) {
@@ -305,10 +343,11 @@ static void drift_noise_f32(const oracle_params *P, const consts_f32 *c, float p
         float ag = c->a * g;
         float one_ag = 1.0f + ag;
         float num = (dphi * c->inv_w2) * ag;
-        float corr = num / one_ag;
-        float d = 2.0f / phi;
+        float corr = num * oracle_recip_f32(one_ag);
+        float y = oracle_recip_f32(phi);
+        float d = y + y;
         *D = corr - d;
-        *S = (c->cm * phi) * sqrtf(one_ag);
+        *S = (c->cm * phi) * oracle_sqrt_f32(one_ag);
     } else {
         *D = 0.0f;
         *S = c->s_flat;
@@ -322,7 +361,7 @@ static float bias_ratio_f32(const oracle_params *P, const consts_f32 *c, float p
     if (P->bias_kind == BIAS_POWER) {
         float pw = 1.0f;
         for (int i = 0; i < P->p; ++i) pw = pw * phi;
-        return (c->A * pw) / S;
+        return (c->A * pw) * oracle_recip_f32(S);
     }
     return 0.0f;
 }
@@ -467,6 +506,16 @@ void oracle_log_f32_batch(const float *x, float *y, int64_t n)
 void oracle_sincos2pi_f32_batch(const float *u, float *c, float *s, int64_t n)
 {
     for (int64_t i = 0; i < n; ++i) oracle_sincos2pi_f32(u[i], &c[i], &s[i]);
+}
+
+void oracle_recip_f32_batch(const float *x, float *y, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) y[i] = oracle_recip_f32(x[i]);
+}
+
+void oracle_sqrt_f32_batch(const float *x, float *y, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) y[i] = oracle_sqrt_f32(x[i]);
 }
 
 void oracle_exp_f32_batch(const float *x, float *y, int64_t n)

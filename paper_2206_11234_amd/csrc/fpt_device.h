@@ -4,8 +4,10 @@
 // Method: arXiv:2206.11234, Sec. 2.1-2.3.  Every binary32 operation below is
 // part of the step semantics shared with the CPU checker: the step count of a
 // run is decided in binary32, so the order of operations and the places where
-// fma is used are fixed (the library is built with -ffp-contract=off, IEEE
-// division and square root, no fast-math).
+// fma is used are fixed (the library is built with -ffp-contract=off and no
+// fast-math).  Reciprocals and square roots are fma-only Newton sequences:
+// cheaper on gfx950 than the IEEE division/sqrt expansions and reproducible
+// operation for operation on any IEEE binary32 machine.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -34,10 +36,13 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
             k0 += 0x9E3779B9u;
             k1 += 0xBB67AE85u;
         }
-        const uint32_t lo_a = 0xD2511F53u * c0;
-        const uint32_t hi_a = __umulhi(0xD2511F53u, c0);
-        const uint32_t lo_b = 0xCD9E8D57u * c2;
-        const uint32_t hi_b = __umulhi(0xCD9E8D57u, c2);
+        // one 32x32->64 multiply per word gives both halves (v_mad_u64_u32)
+        const uint64_t pa = static_cast<uint64_t>(0xD2511F53u) * c0;
+        const uint64_t pb = static_cast<uint64_t>(0xCD9E8D57u) * c2;
+        const uint32_t lo_a = static_cast<uint32_t>(pa);
+        const uint32_t hi_a = static_cast<uint32_t>(pa >> 32);
+        const uint32_t lo_b = static_cast<uint32_t>(pb);
+        const uint32_t hi_b = static_cast<uint32_t>(pb >> 32);
         const uint32_t n0 = hi_b ^ c1 ^ k0;
         const uint32_t n2 = hi_a ^ c3 ^ k1;
         c0 = n0;
@@ -54,6 +59,34 @@ __device__ __forceinline__ float uniform24(uint32_t x) {
     return static_cast<float>(odd) * 0x1p-24f;
 }
 
+// 1/x for positive normal x: Newton-Raphson y <- fma(y, fma(-x, y, 1), y), three
+// steps from the seed bits(0x7EF311C3 - bits(x)) (relative error < 5.1%); the result
+// is within 0.51 ulp.  Division-free: only fma and integer subtract.
+__device__ __forceinline__ float recip_f32(float x) {
+    float y = __uint_as_float(0x7EF311C3u - __float_as_uint(x));
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float e = __builtin_fmaf(-x, y, 1.0f);
+        y = __builtin_fmaf(y, e, y);
+    }
+    return y;
+}
+
+// sqrt x for positive normal x: reciprocal square root by Newton-Raphson
+// y <- fma(y, fma(-x/2, y*y, 1/2), y), three steps from bits(0x5F3759DF - (bits(x) >> 1)),
+// then x*y; within 2 ulp.
+__device__ __forceinline__ float sqrt_f32(float x) {
+    float y = __uint_as_float(0x5F3759DFu - (__float_as_uint(x) >> 1));
+    const float hx = 0.5f * x;
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const float yy = y * y;
+        const float e = __builtin_fmaf(-hx, yy, 0.5f);
+        y = __builtin_fmaf(y, e, y);
+    }
+    return x * y;
+}
+
 // ln x for positive normal x: x = 2^e f, f in [sqrt(1/2), sqrt 2];
 // ln f = 2 atanh(s), s = (f-1)/(f+1), as the odd series to s^9;
 // ln x = e ln2_hi + (e ln2_lo + ln f).
@@ -66,7 +99,7 @@ __device__ __forceinline__ float log_f32(float x) {
         f = __uint_as_float(mant | 0x3F000000u);
         e += 1;
     }
-    const float s = (f - 1.0f) / (f + 1.0f);
+    const float s = (f - 1.0f) * recip_f32(f + 1.0f);
     const float z = s * s;
     float p = 1.0f / 9.0f;
     p = __builtin_fmaf(p, z, 1.0f / 7.0f);
@@ -98,23 +131,16 @@ __device__ __forceinline__ void sincos2pi_f32(float u, float &c_out, float &s_ou
     pc = __builtin_fmaf(pc, r2, 64.939394022668291491f);
     pc = __builtin_fmaf(pc, r2, -19.7392088021787172377f);
     const float cs = __builtin_fmaf(pc, r2, 1.0f);
-    const int iq = static_cast<int>(q) & 3;
-    float c, s;
-    if (iq == 0) {
-        c = cs;
-        s = sn;
-    } else if (iq == 1) {
-        c = -sn;
-        s = cs;
-    } else if (iq == 2) {
-        c = -cs;
-        s = -sn;
-    } else {
-        c = sn;
-        s = -cs;
-    }
-    c_out = c;
-    s_out = s;
+    // quarter-turn rotation by q, branch-free: odd q swaps (cos, sin); the signs of
+    // cos and sin flip for q = 1, 2 and q = 2, 3 respectively (IEEE negation = sign bit)
+    const uint32_t iq = static_cast<uint32_t>(static_cast<int>(q)) & 3u;
+    const bool swap = (iq & 1u) != 0u;
+    const float c0 = swap ? sn : cs;
+    const float s0 = swap ? cs : sn;
+    const uint32_t sign_c = ((iq + 1u) & 2u) << 30;
+    const uint32_t sign_s = (iq & 2u) << 30;
+    c_out = __uint_as_float(__float_as_uint(c0) ^ sign_c);
+    s_out = __uint_as_float(__float_as_uint(s0) ^ sign_s);
 }
 
 // e^x for x <= 0 (x < -80 gives 0): n = rint(x / ln 2), r = x - n ln2 (two-part),
@@ -151,7 +177,7 @@ __device__ __forceinline__ F4 normals4(uint32_t j, uint64_t t, uint32_t stream, 
     {
         const float ua = uniform24(x.x);
         const float ub = uniform24(x.y);
-        const float rho = __builtin_sqrtf(-2.0f * log_f32(ua));
+        const float rho = sqrt_f32(-2.0f * log_f32(ua));
         float c, s;
         sincos2pi_f32(ub, c, s);
         out.a = rho * c;
@@ -160,7 +186,7 @@ __device__ __forceinline__ F4 normals4(uint32_t j, uint64_t t, uint32_t stream, 
     {
         const float ua = uniform24(x.z);
         const float ub = uniform24(x.w);
-        const float rho = __builtin_sqrtf(-2.0f * log_f32(ua));
+        const float rho = sqrt_f32(-2.0f * log_f32(ua));
         float c, s;
         sincos2pi_f32(ub, c, s);
         out.c = rho * c;
@@ -186,7 +212,8 @@ struct StepConsts {
 template <int POT>
 __device__ __forceinline__ void drift_noise(const StepConsts &C, float phi, float &D, float &S) {
     if constexpr (POT == POT_QUADRATIC) {
-        const float d = 2.0f / phi;
+        const float y = recip_f32(phi);
+        const float d = y + y;          // 2/phi
         D = -d;
         S = C.cm * phi;
     } else if constexpr (POT == POT_QUADRATIC_BUMP) {
@@ -197,10 +224,11 @@ __device__ __forceinline__ void drift_noise(const StepConsts &C, float phi, floa
         const float ag = C.a * g;
         const float one_ag = 1.0f + ag;
         const float num = (dphi * C.inv_w2) * ag;
-        const float corr = num / one_ag;
-        const float d = 2.0f / phi;
+        const float corr = num * recip_f32(one_ag);
+        const float y = recip_f32(phi);
+        const float d = y + y;
         D = corr - d;
-        S = (C.cm * phi) * __builtin_sqrtf(one_ag);
+        S = (C.cm * phi) * sqrt_f32(one_ag);
     } else {
         D = 0.0f;
         S = C.cm;
@@ -216,7 +244,7 @@ __device__ __forceinline__ float bias_ratio(const StepConsts &C, float phi, floa
     } else if constexpr (BIAS == BIAS_POWER) {
         float pw = 1.0f;
         for (int i = 0; i < C.p; ++i) pw = pw * phi;
-        return (C.A * pw) / S;
+        return (C.A * pw) * recip_f32(S);
     } else {
         return 0.0f;
     }

@@ -246,12 +246,12 @@ __global__ __launch_bounds__(1024) void fpt_step_kernel(StepArgs a) {
                         const float dlw = -(r * inc);
                         lw += static_cast<double>(dlw);
                     }
-                    if (nphi > C.phi_uv) nphi = C.two_uv - nphi;
+                    nphi = (nphi > C.phi_uv) ? C.two_uv - nphi : nphi;
                     phi = nphi;
                     k += 1;
-                    if (phi <= C.phi_end) st = ST_ENDED;
-                    else if (k >= C.k_max) st = ST_CENSORED;
-                    else if (phi > C.phi_esc) st = ST_ESCAPED;
+                    const int st_esc = (phi > C.phi_esc) ? ST_ESCAPED : ST_RUNNING;
+                    const int st_cap = (k >= C.k_max) ? ST_CENSORED : st_esc;
+                    st = (phi <= C.phi_end) ? ST_ENDED : st_cap;
                 }
             }
         }
