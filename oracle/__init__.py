@@ -278,13 +278,16 @@ class Histogram:
         return self.lse_w[:B] - np.log(self.widths()) - np.log(self.n_traj)
 
     def jackknife_rel_err(self):
-        """Relative error of P_hat_j from the spread over subsets, rescaled by 1/sqrt(n_sub)."""
+        """Relative error of P_hat_j from the spread over subsets, rescaled by 1/sqrt(n_sub):
+        sd_s(P_hat_j^(s)) / sqrt(n_sub) / P_hat_j, with each subset estimate taken relative to
+        P_hat_j, P^(s)/P = exp(lse_s - lse) n_total/n_s (so far-tail values do not underflow)."""
         B = len(self.edges) - 1
-        ps = np.exp(self.jk_lse_w[:, :B]) / (self.widths()[None, :] * self.n_per_sub[:, None])
-        p = np.exp(self.log_p_naive())
-        sd = np.std(ps, axis=0, ddof=1)
-        with np.errstate(invalid="ignore", divide="ignore"):
-            return sd / np.sqrt(self.n_sub) / p
+        with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
+            ratio = np.exp(self.jk_lse_w[:, :B] - self.lse_w[None, :B]) * (self.n_traj / self.n_per_sub[:, None])
+            sd = np.std(ratio, axis=0, ddof=1)
+            out = sd / np.sqrt(self.n_sub)
+        out[~np.isfinite(self.lse_w[:B])] = np.nan
+        return out
 
     def kish_rel_err2(self):
         """sum w^2 / (sum w)^2 - 1/n_total: the delta-method relative variance of P_hat_j."""

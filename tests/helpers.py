@@ -57,7 +57,9 @@ def assert_histogram_matches(res, h, rel=1e-12):
     assert np.all(np.abs(res.log_p[fin] - lp[fin]) <= rel * np.maximum(1, np.abs(lp[fin])))
     jk = h.jackknife_rel_err()
     f2 = np.isfinite(jk) & fin
-    assert np.all(np.abs(res.rel_err_jk[f2] - jk[f2]) <= 1e-8 * np.maximum(1e-3, jk[f2]))
+    bad = np.nonzero(~(np.abs(res.rel_err_jk[f2] - jk[f2]) <= 1e-8 * np.maximum(1e-3, jk[f2])))[0]
+    assert bad.size == 0, ("rel_err_jk", np.nonzero(f2)[0][bad][:5], res.rel_err_jk[f2][bad][:5], jk[f2][bad][:5],
+                           res.count[:B][f2][bad][:5], res.lse_w[:B][f2][bad][:5])
     kish = np.sqrt(np.maximum(h.kish_rel_err2(), 0))
     f3 = np.isfinite(kish) & (h.count[:B] > 0)
     assert np.all(np.abs(res.rel_err_kish[f3] - kish[f3]) <= 1e-8 * np.maximum(1e-3, kish[f3]) + 1e-7)

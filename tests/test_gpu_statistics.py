@@ -1,0 +1,171 @@
+"""Statistical validation of the GPU estimates at full size against what the paper fixes.
+
+* Diffusion-dominated tail (the paper's m = 1, phi_in = phi_UV = sqrt 42 case of Sec. 3.1 and
+  config C2's m = 1, phi_in = 6, wall at 8): P(N) = sum_n a_n exp(-Lambda_n N) (pole expansion,
+  Sec. 1 and App. A) from the oracle's Sturm-Liouville solve, with the absorbing end moved out
+  by beta S sqrt(dN) for the discrete monitoring; compared bin by bin within the estimated
+  error in every bin the paper's own criteria trust.
+* Drift-dominated core (m = 0.01, phi_in = 10): the Gaussian of App. B (gamma = kappa = 0) on
+  the simulation's lattice, within 4 sigma of the mean.
+* The three bias amplitudes of each case estimate the same P(N) where their samples overlap
+  (Sec. 3: different A probe different regions of one distribution).
+* Binary32 against binary64: the same runs through the oracle's binary64 mode differ from the
+  binary32 histogram by a small fraction of the statistical error (stated for config C1).
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+from oracle import refmath as R
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def fpt():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2206_11234_amd as F
+    return F
+
+
+@pytest.fixture(scope="module")
+def c2_results(fpt):
+    insts = W.c2()
+    print("[case] C2 full statistics", flush=True)
+    results, _, _ = fpt.run_batch(insts, 0, block=512, wg_per_cu=2, chunk=1)
+    return insts, results
+
+
+def _bin_average(f, edges, n=64):
+    out = np.empty(len(edges) - 1)
+    for j in range(len(edges) - 1):
+        x = np.linspace(edges[j], edges[j + 1], n + 1)
+        y = f(x)
+        out[j] = np.trapezoid(y, x) / (edges[j + 1] - edges[j])
+    return out
+
+
+def _trusted(res):
+    """Bins whose naive estimate and error are reliable by the paper's own criteria: n_j > 400
+    for the jackknife (Sec. 2.1) and n_j > <w>^2 exp(sigma^2_lnw) for the weight dispersion
+    (Sec. 2.4; <w>^2 is the squared mean of the bin's weights relative to its typical weight,
+    taken as 1 here, so the condition is n_j > exp(sigma^2_lnw))."""
+    B = res.n_bins
+    n = res.count[:B].astype(float)
+    with np.errstate(over="ignore", invalid="ignore"):
+        disp_ok = n > np.exp(np.nan_to_num(res.m2_lnw[:B], nan=np.inf))
+    return (n > 400) & disp_ok & np.isfinite(res.log_p)
+
+
+def _pole_reference(model, edges, dN, n_modes=6):
+    S_end = model.m * model.phi_end / (2 * math.pi * math.sqrt(6))
+    shifted = O.Model(m=model.m, phi_in=model.phi_in, phi_uv=model.phi_uv,
+                      phi_end=model.phi_end - R.BGK_BETA * S_end * math.sqrt(dN))
+    modes = R.sl_modes(shifted, n_modes, lam_max=4.0, n_scan=160)
+    pdf = lambda N: np.sum(modes.amp[None, :] * np.exp(-modes.lam[None, :] * N[:, None]), axis=1)
+    return _bin_average(pdf, edges), modes
+
+
+def test_paper_diffusion_case_matches_pole_expansion(fpt):
+    """Sec. 3.1 / Fig. 3: m = 1, phi_in = phi_UV = sqrt 42, 2e5 runs each for A = 0, 0.4, 0.8.
+    The paper reaches P ~ 1e-3, 1e-6, 1e-12; here every trusted bin (N >= 10, where the six
+    slowest poles have converged) agrees with the pole expansion within its jackknife error,
+    and the reach with A = 0.8 is at least 1e-8 under the dispersion criterion (the paper's
+    1e-12 counts every bin with n_j > 400; that reach is printed too)."""
+    insts = [W.paper_diffusion(A, stream=i) for i, A in enumerate((0.0, 0.4, 0.8))]
+    results, _, _ = fpt.run_batch(insts, 0, block=512, wg_per_cu=2, chunk=1)
+    ref, modes = _pole_reference(O.Model.from_instance(insts[0]), insts[0].edges, insts[0].dN)
+    assert abs(modes.lam[0] - 0.6528232) < 1e-4
+    reach = []
+    for inst, res in zip(insts, results):
+        use = _trusted(res) & (res.edges[:-1] >= 10.0)
+        z = (np.exp(res.log_p[use]) / ref[use] - 1) / res.rel_err_jk[use]
+        reach.append(ref[use].min())
+        n400 = (res.count[:res.n_bins] > 400) & np.isfinite(res.log_p)
+        print(f"{inst.name}: trusted bins {use.sum()}, reach P {ref[use].min():.2e} "
+              f"(n_j > 400 only: {ref[n400].min():.2e}), max|z| {np.max(np.abs(z)):.2f}")
+        assert np.mean(np.abs(z) < 3) > 0.9, (inst.name, z)
+    assert reach[0] > reach[1] > reach[2]
+    assert reach[2] < 1e-8
+
+
+def test_c2_diffusion_tail_matches_pole_expansion(c2_results):
+    """Config C2, diffusion-dominated, A = 1: trusted bins agree with the pole expansion; the
+    reach is reported (the paper notes that with B = A S the weights spread in this regime,
+    which limits how far a fixed bias goes, Sec. 3.1)."""
+    insts, results = c2_results
+    inst, res = insts[3], results[3]
+    ref, _ = _pole_reference(O.Model.from_instance(inst), res.edges, inst.dN)
+    use = _trusted(res) & (res.edges[:-1] >= 10.0)
+    z = (np.exp(res.log_p[use]) / ref[use] - 1) / res.rel_err_jk[use]
+    print(f"C2 diffusion A=1: trusted bins {use.sum()}, reach P {ref[use].min():.2e}, max|z| {np.max(np.abs(z)):.2f}")
+    assert use.sum() >= 10
+    assert np.mean(np.abs(z) < 3) > 0.9
+
+
+def test_drift_core_matches_lattice_gaussian(c2_results):
+    insts, results = c2_results
+    mu, sig = W.MU_SIGMA["C2_drift_T"]
+    model = O.Model(m=0.01, phi_in=10.0)
+    _, tau = R.noise_free_em(model)
+    eps = tau - R.classical_N(model)
+    for inst, res in zip(insts[:3], results[:3]):
+        probs = R.lattice_gaussian_probs(mu, sig, inst.dN, res.edges, eps)
+        ref = probs / np.diff(res.edges)
+        centre = 0.5 * (res.edges[1:] + res.edges[:-1])
+        use = (np.abs(centre - mu) < 4 * sig) & (res.count[:res.n_bins] > 400)
+        if use.sum() < 5:
+            continue
+        z = (np.exp(res.log_p[use]) / ref[use] - 1) / res.rel_err_jk[use]
+        print(inst.name, "core bins", use.sum(), "max |z|", np.max(np.abs(z)))
+        assert np.mean(np.abs(z) < 3) > 0.85, (inst.name, z)
+
+
+def test_bias_amplitudes_agree_where_samples_overlap(c2_results):
+    """Bins trusted in two runs with different A estimate the same P(N)."""
+    insts, results = c2_results
+    for group in (results[:3], results[3:]):
+        for a in range(3):
+            for b in range(a + 1, 3):
+                ra, rb = group[a], group[b]
+                use = _trusted(ra) & _trusted(rb)
+                if use.sum() == 0:
+                    continue
+                d = ra.log_p[use] - rb.log_p[use]
+                err = np.sqrt(ra.rel_err_jk[use] ** 2 + rb.rel_err_jk[use] ** 2)
+                z = d / err
+                print(f"A pair {a},{b}: {use.sum()} bins, max|z| {np.max(np.abs(z)):.2f}")
+                assert np.mean(np.abs(z) < 3) > 0.85, (a, b, z)
+
+
+def test_weights_average_to_one_with_censored_runs(c2_results):
+    """E_S[w] = 1 over every launched run, censored and escaped ones included."""
+    insts, results = c2_results
+    for inst, res in zip(insts, results):
+        mean_w = math.exp(res.lse_w_all) / inst.n_traj
+        ess = math.exp(2 * res.lse_w_all - res.lse_w2_all)
+        if ess > 1000:
+            assert abs(mean_w - 1) < 6 / math.sqrt(ess), (inst.name, mean_w, ess)
+
+
+def test_binary32_vs_binary64_on_c1(fpt):
+    """Config C1: the binary32 histogram and the binary64 oracle's histogram of the same 1e4
+    runs agree to a fraction of the statistical error (the error of every binary32 result
+    against binary64 is stated by this comparison)."""
+    inst = W.c1()
+    res, _, _ = fpt.run(inst, 0, block=512, wg_per_cu=2, chunk=1)
+    tr64 = O.simulate(O.Model.from_instance(inst), 0, inst.n_traj, mode=O.MODE_F64)
+    h64 = O.histogram(tr64, inst.dN, inst.edges)
+    c32 = res.count[:100].astype(float)
+    c64 = h64.count[:100].astype(float)
+    # per-bin count difference in units of the Poisson error of the bin
+    err = np.sqrt(np.maximum(c64, 1.0))
+    z = (c32 - c64) / err
+    print("binary32 - binary64 per-bin |z| max", np.max(np.abs(z)), "rms", np.sqrt(np.mean(z ** 2)))
+    assert np.sqrt(np.mean(z ** 2)) < 0.5
+    assert abs(res.total_steps - int(tr64.k.sum())) / int(tr64.k.sum()) < 1e-4

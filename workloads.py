@@ -170,6 +170,16 @@ def c5(n_traj: int = 1_000_000_000) -> Instance:
                     dN=1e-4, n_traj=n_traj, k_max=kmax, edges=log_edges(mu - 6 * sig, mu + 40 * sig, 500))
 
 
+def paper_diffusion(A: float, n_traj: int = 200_000, stream: int = 0) -> Instance:
+    """The diffusion-dominated validation case of Sec. 3.1 (Fig. 3): m = 1,
+    phi_in = phi_UV = sqrt 42, A in {0, 0.4, 0.8}, 2e5 runs each.  dN is not stated
+    in the paper; 1e-3 is used."""
+    phi = math.sqrt(42.0)
+    return Instance(f"V2_A{A}", m=1.0, phi_in=phi, phi_uv=phi, bias=BIAS_NOISE_SCALED if A else BIAS_NONE,
+                    A=A, dN=1e-3, n_traj=n_traj, k_max=K_MAX_CAP, stream=stream,
+                    edges=np.linspace(0.0, 80.0, 161))
+
+
 def flat_well(L: float = 1.5, x: float = 1.0, V0: float = 1.0, dN: float = 1e-3, n_traj: int = 100_000,
               A: float = 0.0, wall: bool = True) -> Instance:
     """Quantum well (constant V, Sec. 3): Brownian motion from x, absorbing at 0,
