@@ -82,15 +82,21 @@ typedef struct pyfpt_potential {
     double V0;                       /* flat potential */
 } pyfpt_potential;
 
-/* Learned proposal: a 3 -> H -> H -> 1 tanh network giving r = B/S from
- * (phi, k dN, N*), each input affinely normalised: in_i = (x_i - mean_i) * inv_scale_i.
- * Weights are bfloat16 on the device, row-major W[out][in]; biases float.
- * Layout of `params` (device memory): see pyfpt_mlp_layout(). */
+/* Learned proposal: a 3 -> 64 -> 64 -> 1 tanh network giving the bias in noise units,
+ * r = B/S = out_scale * (w3 . h2 + b3), h2 = tanh(W2 h1 + b2), h1 = tanh(W1 x + b1), from
+ * x_i = (in_i - in_mean_i) * in_inv_scale_i with in = (phi, k dN, N*).  Any such bias leaves
+ * the weighted estimator unbiased (the weight of Sec. 2.2 holds for any adapted drift).
+ * `params` (device memory) holds the 4481 parameters as bfloat16, in this order:
+ *   W1[64][3], b1[64], W2[64][64], b2[64], w3[64], b3        (row-major, W[out][in]).
+ * The network is evaluated on the matrix cores with binary32 accumulation and bfloat16
+ * activations, every step (eval_every = 1) or once per group of four steps at the group's
+ * first step (eval_every = 4; the bias is then held for the group). */
 typedef struct pyfpt_mlp {
-    const void *params;              /* device pointer (bf16 weights + f32 biases, pyfpt_mlp_layout) */
-    int32_t hidden;                  /* H: 64 */
+    const void *params;              /* device pointer, 4481 bfloat16 */
+    int32_t hidden;                  /* must be 64 */
     float in_mean[3], in_inv_scale[3];
-    float out_scale;                 /* r = out_scale * (network output) */
+    float out_scale;
+    int32_t eval_every;              /* 1 or 4 */
 } pyfpt_mlp;
 
 typedef struct pyfpt_bias {
@@ -174,7 +180,8 @@ typedef struct pyfpt_dump {
 
 typedef struct pyfpt_options {
     void *stream;                    /* hipStream_t; NULL = null stream */
-    int32_t block;                   /* threads per workgroup (64..1024, multiple of 64); 0 = autotune */
+    int32_t block;                   /* threads per workgroup (64..1024, multiple of 64; <= 256 for the
+                                        learned bias); 0 = autotune */
     int32_t chunk;                   /* queue claim multiplier per wave (>= 1); 0 = autotune */
     int32_t wg_per_cu;               /* persistent workgroups per CU; 0 = autotune */
     int32_t use_graph;               /* capture the launch sequence in a hipGraph and replay it */
@@ -208,7 +215,8 @@ int pyfpt_run(const pyfpt_potential *pot, double phi_in, double phi_end, double 
  * Batch: n_inst instances (1..1024) in one persistent launch over a shared
  * work queue ordered longest-expected-run first; out is an array of n_inst
  * results.  All instances must share the potential kind and bias kind
- * (otherwise EUNSUPPORTED), except that PYFPT_BIAS_NONE and
+ * (otherwise EUNSUPPORTED; learned-bias instances must also share the network
+ * parameters and eval_every), except that PYFPT_BIAS_NONE and
  * PYFPT_BIAS_NOISE_SCALED mix (no bias is the noise-scaled bias with A = 0,
  * with identical results).  Same validation as pyfpt_run per instance.
  */
@@ -219,6 +227,16 @@ int pyfpt_run_batch(const pyfpt_instance *inst, int32_t n_inst, uint64_t seed,
  * (block/wg_per_cu as resolved; 0 fields take the defaults). */
 int pyfpt_workspace_size(const pyfpt_instance *inst, int32_t n_inst, const pyfpt_options *opt,
                          size_t *bytes);
+
+/*
+ * The learned bias on its own (for checks and for tools): r[i] = r_theta(phi[i], N[i], N*)
+ * for i < n, with the same matrix-core evaluation as inside the step loop.  phi, N and r are
+ * device arrays of n binary32 values; work is enqueued on `stream` (a hipStream_t, NULL =
+ * null stream) and the call returns once it is enqueued.  EINVAL for a NULL pointer with
+ * n > 0 or hidden != 64.
+ */
+int pyfpt_mlp_forward(const pyfpt_mlp *mlp, double target_N, const float *phi, const float *N, float *r,
+                      uint64_t n, void *stream);
 
 /* Number of compute units of the current device (0 if none). */
 int pyfpt_device_cus(int32_t *cus);

@@ -31,7 +31,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(HERE, "_liboracle.so")
 
 POT_QUADRATIC, POT_QUADRATIC_BUMP, POT_FLAT = 0, 1, 2
-BIAS_NONE, BIAS_NOISE_SCALED, BIAS_POWER = 0, 1, 2
+BIAS_NONE, BIAS_NOISE_SCALED, BIAS_POWER, BIAS_MLP = 0, 1, 2, 3
 ST_ENDED, ST_CENSORED, ST_ESCAPED = 1, 2, 3
 MODE_F32, MODE_F64 = 0, 1
 
@@ -49,6 +49,11 @@ class _Params(ctypes.Structure):
         ("k_max", ctypes.c_uint64),
         ("seed", ctypes.c_uint64),
         ("stream", ctypes.c_uint32),
+        ("mlp", ctypes.POINTER(ctypes.c_float)),
+        ("in_mean", ctypes.c_float * 3), ("in_inv", ctypes.c_float * 3),
+        ("out_scale", ctypes.c_float),
+        ("target_N", ctypes.c_double),
+        ("eval_every", ctypes.c_int),
     ]
 
 
@@ -89,6 +94,7 @@ def lib():
                                       ctypes.c_uint64, ctypes.c_int, u64p, f64p, f64p, i32p,
                                       ctypes.c_int]
         L.oracle_simulate.restype = ctypes.c_int
+        L.oracle_mlp_r_batch.argtypes = [ctypes.POINTER(_Params), f32p, f32p, f64p, ctypes.c_int64]
         _lib = L
     return _lib
 
@@ -119,6 +125,8 @@ class Model:
     dN: float = 1e-3
     k_max: int = 1 << 20
     stream: int = 0
+    mlp: object = None            # MlpParams for the learned bias
+    target_N: float = 0.0
 
     @staticmethod
     def from_instance(inst) -> "Model":
@@ -126,7 +134,7 @@ class Model:
         return Model(pot=inst.pot, m=inst.m, a=inst.a, phi0=inst.phi0, w=inst.w, V0=inst.V0,
                      bias=inst.bias, A=inst.A, p=inst.p, phi_in=inst.phi_in, phi_end=inst.phi_end,
                      phi_uv=inst.phi_uv, phi_esc=inst.phi_esc, dN=inst.dN, k_max=inst.k_max,
-                     stream=inst.stream)
+                     stream=inst.stream, mlp=getattr(inst, "mlp", None), target_N=getattr(inst, "target_N", 0.0))
 
     def esc(self) -> float:
         if np.isfinite(self.phi_uv):
@@ -134,9 +142,19 @@ class Model:
         return self.phi_esc if self.phi_esc > 0 else 100.0 * self.phi_in
 
     def to_c(self, seed: int) -> _Params:
-        return _Params(self.pot, self.m, self.a, self.phi0, self.w, self.V0, self.bias, self.A,
-                       self.p, self.phi_in, self.phi_end, self.phi_uv, self.esc(), self.dN,
-                       int(self.k_max), int(seed), int(self.stream))
+        P = _Params(self.pot, self.m, self.a, self.phi0, self.w, self.V0, self.bias, self.A,
+                    self.p, self.phi_in, self.phi_end, self.phi_uv, self.esc(), self.dN,
+                    int(self.k_max), int(seed), int(self.stream))
+        if self.mlp is not None:
+            m = self.mlp
+            self._mlp_keep = np.ascontiguousarray(m.values_f32(), np.float32)
+            P.mlp = self._mlp_keep.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+            P.in_mean[:] = [float(v) for v in m.in_mean]
+            P.in_inv[:] = [float(v) for v in m.in_inv_scale]
+            P.out_scale = float(m.out_scale)
+            P.target_N = float(self.target_N)
+            P.eval_every = int(m.eval_every)
+        return P
 
 
 @dataclass
@@ -164,6 +182,17 @@ def simulate(model: Model, seed: int, n: int, t0: int = 0, stride: int = 1,
                              _ptr(st, ctypes.c_int32), int(threads))
     t = (np.uint64(t0) + np.arange(n, dtype=np.uint64) * np.uint64(stride)).astype(np.uint64)
     return Trajectories(t, k, lw, phi, st, used)
+
+
+def mlp_r(model: Model, phi, N) -> np.ndarray:
+    """The learned bias r at the given (phi, N) points (binary64 with bfloat16 roundings)."""
+    phi = np.ascontiguousarray(phi, np.float32)
+    N = np.ascontiguousarray(N, np.float32)
+    out = np.zeros(phi.size, np.float64)
+    P = model.to_c(0)
+    lib().oracle_mlp_r_batch(ctypes.byref(P), _ptr(phi, ctypes.c_float), _ptr(N, ctypes.c_float),
+                             _ptr(out, ctypes.c_double), phi.size)
+    return out
 
 
 def philox(ctr, key):

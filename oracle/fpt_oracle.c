@@ -278,7 +278,7 @@ void oracle_normals_f64(uint64_t seed, uint32_t stream, uint64_t t, uint32_t j, 
 /* Model description.                                                   */
 /* ------------------------------------------------------------------ */
 enum { POT_QUADRATIC = 0, POT_QUADRATIC_BUMP = 1, POT_FLAT = 2 };
-enum { BIAS_NONE = 0, BIAS_NOISE_SCALED = 1, BIAS_POWER = 2 };
+enum { BIAS_NONE = 0, BIAS_NOISE_SCALED = 1, BIAS_POWER = 2, BIAS_MLP = 3 };
 enum { ST_RUNNING = 0, ST_ENDED = 1, ST_CENSORED = 2, ST_ESCAPED = 3 };
 enum { MODE_F32 = 0, MODE_F64 = 1 };
 
@@ -294,7 +294,58 @@ typedef struct {
     uint64_t k_max;
     uint64_t seed;
     uint32_t stream;
+    /* learned bias: 4481 parameters (bfloat16 values stored as float) in the order
+     * W1[64][3], b1[64], W2[64][64], b2[64], w3[64], b3; inputs (phi, k dN, N*) */
+    const float *mlp;
+    float in_mean[3], in_inv[3];
+    float out_scale;
+    double target_N;
+    int eval_every;
 } oracle_params;
+
+/* round a binary32 value to the nearest bfloat16 (ties to even), returned as binary32 */
+static float bf16_round(float x)
+{
+    uint32_t b;
+    memcpy(&b, &x, 4);
+    if ((b & 0x7F800000u) == 0x7F800000u) return x;     /* inf / nan unchanged */
+    b = (b + 0x7FFFu + ((b >> 16) & 1u)) & 0xFFFF0000u;
+    float y;
+    memcpy(&y, &b, 4);
+    return y;
+}
+
+/* The learned bias r = out_scale (w3 . h2 + b3), h2 = tanh(W2 h1 + b2), h1 = tanh(W1 x + b1),
+ * in binary64 with the kernel's bfloat16 roundings: inputs and both hidden activations are
+ * rounded to bfloat16 before they multiply the next layer's weights. */
+double oracle_mlp_r(const oracle_params *P, float phi, float N)
+{
+    const float *W1 = P->mlp, *b1 = P->mlp + 192, *W2 = P->mlp + 256, *b2 = P->mlp + 4352;
+    const float *w3 = P->mlp + 4416, b3 = P->mlp[4480];
+    float x[3];
+    x[0] = bf16_round((phi - P->in_mean[0]) * P->in_inv[0]);
+    x[1] = bf16_round((N - P->in_mean[1]) * P->in_inv[1]);
+    x[2] = bf16_round(((float)P->target_N - P->in_mean[2]) * P->in_inv[2]);
+    double h1[64], h2[64];
+    for (int u = 0; u < 64; ++u) {
+        double a = (double)b1[u];
+        for (int s = 0; s < 3; ++s) a += (double)W1[u * 3 + s] * (double)x[s];
+        h1[u] = (double)bf16_round((float)tanh(a));
+    }
+    for (int u = 0; u < 64; ++u) {
+        double a = (double)b2[u];
+        for (int v = 0; v < 64; ++v) a += (double)W2[u * 64 + v] * h1[v];
+        h2[u] = (double)bf16_round((float)tanh(a));
+    }
+    double o = (double)b3;
+    for (int u = 0; u < 64; ++u) o += (double)w3[u] * h2[u];
+    return (double)P->out_scale * o;
+}
+
+void oracle_mlp_r_batch(const oracle_params *P, const float *phi, const float *N, double *r, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) r[i] = oracle_mlp_r(P, phi[i], N[i]);
+}
 
 /* Derived constants (Planck units):
  *   quadratic:  D = -2/phi,  S = c_m phi,  c_m = m/(2 pi sqrt 6)
@@ -399,13 +450,21 @@ static int simulate_f32(const oracle_params *P, const consts_f32 *c, uint64_t t,
     double lw = 0.0;
     uint64_t k = 0;
     float xi4[4];
+    float r_mlp = 0.0f;
     int status = ST_RUNNING;
     while (status == ST_RUNNING) {
         if ((k & 3u) == 0) oracle_normals_f32(P->seed, P->stream, t, (uint32_t)(k >> 2), xi4);
         float xi = xi4[k & 3u];
         float D, S;
         drift_noise_f32(P, c, phi, &D, &S);
-        float r = bias_ratio_f32(P, c, phi, S);
+        float r;
+        if (P->bias_kind == BIAS_MLP) {
+            /* evaluated at every step, or at the first step of each group of four */
+            if (P->eval_every == 1 || (k & 3u) == 0) r_mlp = (float)oracle_mlp_r(P, phi, (float)k * c->dN);
+            r = r_mlp;
+        } else {
+            r = bias_ratio_f32(P, c, phi, S);
+        }
         float B = r * S;
         float drift = D + B;
         float det = fmaf(drift, c->dN, phi);
@@ -435,13 +494,20 @@ static int simulate_f64(const oracle_params *P, uint64_t t, uint64_t *k_out, dou
     uint64_t k = 0;
     double xi4[4];
     const double sq = sqrt(P->dN);
+    double r_mlp = 0.0;
     int status = ST_RUNNING;
     while (status == ST_RUNNING) {
         if ((k & 3u) == 0) oracle_normals_f64(P->seed, P->stream, t, (uint32_t)(k >> 2), xi4);
         double xi = xi4[k & 3u];
         double D, S;
         drift_noise_f64(P, phi, &D, &S);
-        double r = bias_ratio_f64(P, phi, S);
+        double r;
+        if (P->bias_kind == BIAS_MLP) {
+            if (P->eval_every == 1 || (k & 3u) == 0) r_mlp = oracle_mlp_r(P, (float)phi, (float)((double)k * P->dN));
+            r = r_mlp;
+        } else {
+            r = bias_ratio_f64(P, phi, S);
+        }
         double nphi = phi + (D + r * S) * P->dN + S * sq * xi;
         lw += -r * (0.5 * r * P->dN + sq * xi);
         if (nphi > P->phi_uv) nphi = 2.0 * P->phi_uv - nphi;

@@ -8,8 +8,8 @@ this package is the thin Python binding over it.
 """
 from ._lib import (BIAS_MLP, BIAS_NOISE_SCALED, BIAS_NONE, BIAS_POWER, POT_FLAT, POT_QUADRATIC,
                    POT_QUADRATIC_BUMP, ST_CENSORED, ST_ENDED, ST_ESCAPED, PyfptError)
-from .api import Dump, Result, device_cus, layout, run, run_batch, run_single_abi
+from .api import Dump, Result, device_cus, layout, mlp_forward, run, run_batch, run_single_abi
 
-__all__ = ["run", "run_batch", "run_single_abi", "layout", "device_cus", "Result", "Dump", "PyfptError",
+__all__ = ["run", "run_batch", "run_single_abi", "layout", "device_cus", "mlp_forward", "Result", "Dump", "PyfptError",
            "POT_QUADRATIC", "POT_QUADRATIC_BUMP", "POT_FLAT", "BIAS_NONE", "BIAS_NOISE_SCALED", "BIAS_POWER",
            "BIAS_MLP", "ST_ENDED", "ST_CENSORED", "ST_ESCAPED"]

@@ -25,7 +25,7 @@ class pyfpt_potential(ctypes.Structure):
 class pyfpt_mlp(ctypes.Structure):
     _fields_ = [("params", ctypes.c_void_p), ("hidden", ctypes.c_int32),
                 ("in_mean", ctypes.c_float * 3), ("in_inv_scale", ctypes.c_float * 3),
-                ("out_scale", ctypes.c_float)]
+                ("out_scale", ctypes.c_float), ("eval_every", ctypes.c_int32)]
 
 
 class pyfpt_bias(ctypes.Structure):
@@ -74,7 +74,7 @@ class pyfpt_options(ctypes.Structure):
 
 # every entry point declared in include/pyfpt.h
 EXPORTS = ("pyfpt_result_layout", "pyfpt_run", "pyfpt_run_batch", "pyfpt_workspace_size",
-           "pyfpt_device_cus", "pyfpt_last_error")
+           "pyfpt_mlp_forward", "pyfpt_device_cus", "pyfpt_last_error")
 
 _lib = None
 
@@ -102,6 +102,8 @@ def load() -> ctypes.CDLL:
                                   P(pyfpt_options)]
     L.pyfpt_workspace_size.argtypes = [P(pyfpt_instance), ctypes.c_int32, P(pyfpt_options), P(ctypes.c_size_t)]
     L.pyfpt_device_cus.argtypes = [P(ctypes.c_int32)]
+    L.pyfpt_mlp_forward.argtypes = [P(pyfpt_mlp), ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
+                                    ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
     L.pyfpt_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         getattr(L, name).restype = ctypes.c_int if name != "pyfpt_last_error" else ctypes.c_char_p

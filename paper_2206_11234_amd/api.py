@@ -146,6 +146,22 @@ def _f(obj, name, default=0.0):
     return getattr(obj, name, default)
 
 
+def mlp_struct(params, keep: list) -> L.pyfpt_mlp:
+    """Device copy (bfloat16 bits) of a network's parameters and its constants."""
+    torch = _torch()
+    bits = params.bf16_bits().view(np.int16)
+    t = torch.from_numpy(bits.copy()).to(torch.device("cuda", torch.cuda.current_device()))
+    keep.append(t)
+    m = L.pyfpt_mlp()
+    m.params = ctypes.c_void_p(t.data_ptr())
+    m.hidden = 64
+    m.in_mean[:] = [float(v) for v in params.in_mean]
+    m.in_inv_scale[:] = [float(v) for v in params.in_inv_scale]
+    m.out_scale = float(params.out_scale)
+    m.eval_every = int(params.eval_every)
+    return m
+
+
 def make_instance(inst, n_sub: int, keep: list) -> L.pyfpt_instance:
     edges = np.ascontiguousarray(np.asarray(inst.edges, dtype=np.float64))
     keep.append(edges)
@@ -156,6 +172,15 @@ def make_instance(inst, n_sub: int, keep: list) -> L.pyfpt_instance:
     I.bias.p = int(_f(inst, "p", 1))
     I.bias.A = float(_f(inst, "A", 0.0))
     I.bias.target_N = float(_f(inst, "target_N", 0.0))
+    if I.bias.kind == L.BIAS_MLP:
+        cache = keep[0] if keep and isinstance(keep[0], dict) else None
+        key = id(inst.mlp)
+        if cache is not None and key in cache:
+            I.bias.mlp = cache[key]
+        else:
+            I.bias.mlp = mlp_struct(inst.mlp, keep)
+            if cache is not None:
+                cache[key] = I.bias.mlp
     I.phi_in = float(inst.phi_in)
     I.phi_end = float(inst.phi_end)
     I.phi_uv = float(_f(inst, "phi_uv", math.inf))
@@ -175,7 +200,7 @@ def run_batch(instances, seed: int = 0, *, n_sub: int = 16, block: int = 0, chun
     """Run a batch of instances in one persistent launch.  Returns (results, dumps, timing_ms)."""
     torch = _torch()
     lib = L.load()
-    keep: list = []
+    keep: list = [{}]          # [0]: device copies of networks shared by several instances
     n = len(instances)
     arr = (L.pyfpt_instance * n)(*[make_instance(i, n_sub, keep) for i in instances])
     dev = torch.device("cuda", torch.cuda.current_device())
@@ -250,6 +275,23 @@ def run_single_abi(inst, seed: int = 0, *, n_sub: int = 16, block: int = 512, ch
     L.check(lib.pyfpt_run(ctypes.byref(I.pot), I.phi_in, I.phi_end, I.phi_uv, I.dN, ctypes.byref(I.bias), I.n_traj,
                           int(seed), ctypes.byref(I.bins), ctypes.byref(res), ctypes.byref(opt)))
     return Result(np.asarray(inst.edges, np.float64), n_sub, counts, values, lay)
+
+
+def mlp_forward(params, target_N: float, phi, N) -> np.ndarray:
+    """r_theta at the given points through pyfpt_mlp_forward (matrix-core evaluation)."""
+    torch = _torch()
+    keep: list = []
+    dev = torch.device("cuda", torch.cuda.current_device())
+    m = mlp_struct(params, keep)
+    p = torch.as_tensor(np.ascontiguousarray(phi, np.float32), device=dev)
+    n_ = torch.as_tensor(np.ascontiguousarray(N, np.float32), device=dev)
+    r = torch.empty_like(p)
+    stream = torch.cuda.current_stream()
+    L.check(L.load().pyfpt_mlp_forward(ctypes.byref(m), float(target_N), ctypes.c_void_p(p.data_ptr()),
+                                       ctypes.c_void_p(n_.data_ptr()), ctypes.c_void_p(r.data_ptr()), p.numel(),
+                                       ctypes.c_void_p(stream.cuda_stream)))
+    stream.synchronize()
+    return r.cpu().numpy()
 
 
 def device_cus() -> int:

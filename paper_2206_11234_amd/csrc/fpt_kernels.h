@@ -5,12 +5,14 @@
 #include <stdint.h>
 
 #include "fpt_device.h"
+#include "fpt_mlp.h"
 
 namespace fpt {
 
 // One instance as the step kernel sees it (uploaded per call).
 struct InstDev {
     StepConsts c;
+    MlpConsts mlp;        // learned proposal: input normalisation, output scale, N*
     uint32_t stream;      // Philox counter word 3
     uint32_t n_bins;
     uint32_t row_base;    // first row of this instance in the per-workgroup table
@@ -59,6 +61,8 @@ struct StepArgs {
     TableLayout lay;
     DumpDev dump;
     uint32_t chunk;
+    const uint16_t *mlp_params;   // bfloat16 network shared by the batch (learned proposal)
+    int32_t mlp_every;            // evaluate the network every 1 or 4 steps
 };
 
 // Per-instance merge metadata.
@@ -122,6 +126,8 @@ hipError_t launch_init_queue(unsigned long long *queue, hipStream_t stream);
 hipError_t launch_step(int pot, int bias, bool tables_in_lds, int n_wg, int block, size_t lds_bytes,
                        const StepArgs &args, hipStream_t stream);
 hipError_t launch_merge(const MergeArgs &args, int total_rows, int n_sub, hipStream_t stream);
+hipError_t launch_mlp_forward(const uint16_t *params, MlpConsts c, const float *phi, const float *N, float *r,
+                              uint64_t n, hipStream_t stream);
 size_t max_lds_bytes();
 
 }  // namespace fpt

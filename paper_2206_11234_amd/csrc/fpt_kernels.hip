@@ -131,9 +131,11 @@ __device__ __forceinline__ void acc_commit_direct(const Tab &T, const LaneAcc &a
     atomic_add_f64(s + 5, a.steps);
 }
 
+extern __shared__ __align__(16) unsigned char fpt_lds[];
+
 template <int POT, int BIAS, bool LDS>
-__global__ __launch_bounds__(1024) void fpt_step_kernel(StepArgs a) {
-    extern __shared__ __align__(16) unsigned char lds[];
+__device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
+    unsigned char *lds = fpt_lds;
     unsigned char *gslice = a.slices + static_cast<size_t>(blockIdx.x) * a.lay.slice_bytes;
     unsigned char *base = LDS ? lds : gslice;
     init_table(base, a.lay);
@@ -160,6 +162,10 @@ __global__ __launch_bounds__(1024) void fpt_step_kernel(StepArgs a) {
     acc_reset(acc, -1);
     // this wave's reserved queue range
     uint64_t res_lo = 0, res_hi = 0;
+    // learned proposal: this wave's share of the network's A operands
+    MlpTiles tiles;
+    if constexpr (BIAS == BIAS_MLP) mlp_load_tiles(a.mlp_params, tiles);
+    MlpConsts mc{};
 
     while (true) {
         // ---- refill: hand new trajectory ids to lanes that need one
@@ -201,6 +207,7 @@ __global__ __launch_bounds__(1024) void fpt_step_kernel(StepArgs a) {
                         row_base = I.row_base;
                         thr_base = I.thr_base;
                         dump_slot = I.dump_slot;
+                        if constexpr (BIAS == BIAS_MLP) mc = I.mlp;
                         cur_inst = ii;
                     }
                     if (acc.inst != ii) {
@@ -220,12 +227,18 @@ __global__ __launch_bounds__(1024) void fpt_step_kernel(StepArgs a) {
         if (!__any(active)) break;
 
         // ---- four Euler-Maruyama steps from one Philox call
-        if (active) {
-            const F4 z = normals4(k >> 2, t, stream, a.key0, a.key1);
-            const float zs[4] = {z.a, z.b, z.c, z.d};
+        // (the learned bias is evaluated by all 64 lanes together, outside divergent code)
+        float r_mlp = 0.0f;
+        if constexpr (BIAS == BIAS_MLP) r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
+        F4 z{};
+        if (active) z = normals4(k >> 2, t, stream, a.key0, a.key1);
+        const float zs[4] = {z.a, z.b, z.c, z.d};
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                if (st == ST_RUNNING) {
+        for (int s = 0; s < 4; ++s) {
+            if constexpr (BIAS == BIAS_MLP) {
+                if (s > 0 && a.mlp_every == 1) r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
+            }
+            if (active && st == ST_RUNNING) {
                     const float xi = zs[s];
                     float D, S;
                     drift_noise<POT>(C, phi, D, S);
@@ -234,7 +247,8 @@ __global__ __launch_bounds__(1024) void fpt_step_kernel(StepArgs a) {
                         r = 0.0f;
                         drift = D;
                     } else {
-                        r = bias_ratio<BIAS>(C, phi, S);
+                        if constexpr (BIAS == BIAS_MLP) r = r_mlp;
+                        else r = bias_ratio<BIAS>(C, phi, S);
                         const float B = r * S;
                         drift = D + B;
                     }
@@ -252,7 +266,6 @@ __global__ __launch_bounds__(1024) void fpt_step_kernel(StepArgs a) {
                     const int st_esc = (phi > C.phi_esc) ? ST_ESCAPED : ST_RUNNING;
                     const int st_cap = (k >= C.k_max) ? ST_CENSORED : st_esc;
                     st = (phi <= C.phi_end) ? ST_ENDED : st_cap;
-                }
             }
         }
 
@@ -342,6 +355,19 @@ __global__ __launch_bounds__(1024) void fpt_step_kernel(StepArgs a) {
         const uint32_t n_words = a.lay.slice_bytes / 8;
         for (uint32_t i = threadIdx.x; i < n_words; i += blockDim.x) dst[i] = src[i];
     }
+}
+
+// Workgroups of up to 1024 threads for the closed-form biases; the learned bias holds the
+// network's operands in registers and runs with up to 256 threads (one wave per SIMD can use
+// the whole register file).
+template <int POT, int BIAS, bool LDS>
+__global__ __launch_bounds__(1024) void fpt_step_kernel(StepArgs a) {
+    fpt_step_body<POT, BIAS, LDS>(a);
+}
+
+template <int POT, bool LDS>
+__global__ __launch_bounds__(256) void fpt_step_mlp_kernel(StepArgs a) {
+    fpt_step_body<POT, BIAS_MLP, LDS>(a);
 }
 
 __global__ void fpt_init_queue_kernel(unsigned long long *q) {
@@ -484,12 +510,30 @@ __global__ __launch_bounds__(256) void fpt_finalize_kernel(MergeArgs a) {
     }
 }
 
+// The learned bias on its own: r_theta at n given (phi, N) points (waves run full; lanes past
+// n compute on a copy of the last point and do not write).
+__global__ __launch_bounds__(256) void fpt_mlp_forward_kernel(const uint16_t *params, MlpConsts c, const float *phi,
+                                                             const float *N, float *r, uint64_t n) {
+    MlpTiles tiles;
+    mlp_load_tiles(params, tiles);
+    const uint64_t i = static_cast<uint64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const uint64_t j = i < n ? i : n - 1;
+    const float out = mlp_forward(tiles, c, phi[j], N[j]);
+    if (i < n) r[i] = out;
+}
+
 // ---------------------------------------------------------------------------
 // launches
 // ---------------------------------------------------------------------------
 template <int POT, int BIAS, bool LDS>
 static hipError_t launch_step_t(int n_wg, int block, size_t lds_bytes, const StepArgs &args, hipStream_t stream) {
-    auto kern = fpt_step_kernel<POT, BIAS, LDS>;
+    void (*kern)(StepArgs);
+    if constexpr (BIAS == BIAS_MLP) {
+        if (block > 256) return hipErrorInvalidConfiguration;
+        kern = fpt_step_mlp_kernel<POT, LDS>;
+    } else {
+        kern = fpt_step_kernel<POT, BIAS, LDS>;
+    }
     if (LDS && lds_bytes > 0) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(kern),
                                            hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds_bytes));
@@ -505,6 +549,7 @@ static hipError_t launch_step_b(int bias, int n_wg, int block, size_t lds, const
     case BIAS_NONE: return launch_step_t<POT, BIAS_NONE, LDS>(n_wg, block, lds, a, s);
     case BIAS_NOISE_SCALED: return launch_step_t<POT, BIAS_NOISE_SCALED, LDS>(n_wg, block, lds, a, s);
     case BIAS_POWER: return launch_step_t<POT, BIAS_POWER, LDS>(n_wg, block, lds, a, s);
+    case BIAS_MLP: return launch_step_t<POT, BIAS_MLP, LDS>(n_wg, block, lds, a, s);
     default: return hipErrorInvalidValue;
     }
 }
@@ -527,6 +572,15 @@ hipError_t launch_step(int pot, int bias, bool tables_in_lds, int n_wg, int bloc
 
 hipError_t launch_init_queue(unsigned long long *queue, hipStream_t stream) {
     hipLaunchKernelGGL(fpt_init_queue_kernel, dim3(1), dim3(64), 0, stream, queue);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const uint16_t *params, MlpConsts c, const float *phi, const float *N, float *r,
+                              uint64_t n, hipStream_t stream) {
+    if (n == 0) return hipSuccess;
+    const uint64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(fpt_mlp_forward_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, stream, params, c,
+                       phi, N, r, n);
     return hipGetLastError();
 }
 

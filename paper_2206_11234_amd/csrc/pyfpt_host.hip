@@ -113,6 +113,8 @@ struct Prepared {
     std::vector<MergeInst> mi;
     std::vector<ResultLayout> rl;
     TableLayout lay{};
+    const uint16_t *mlp_params = nullptr;
+    int mlp_every = 1;
     uint64_t v_total = 0;
     uint64_t counts_total = 0, values_total = 0;
     int pot = 0, bias = 0;
@@ -163,8 +165,16 @@ int validate(const pyfpt_instance &I, int i) {
     case PYFPT_BIAS_POWER:
         if (!finite(B.A) || B.p < 0 || B.p > 16) return fail(PYFPT_EINVAL, "instance %d: power bias needs finite A and 0 <= p <= 16", i);
         break;
-    case PYFPT_BIAS_MLP:
-        return fail(PYFPT_EUNSUPPORTED, "instance %d: the learned proposal is run by pyfpt_run_mlp", i);
+    case PYFPT_BIAS_MLP: {
+        const pyfpt_mlp &M = B.mlp;
+        if (!M.params) return fail(PYFPT_EINVAL, "instance %d: learned bias needs device parameters", i);
+        if (M.hidden != 64) return fail(PYFPT_EINVAL, "instance %d: learned bias supports hidden = 64 only", i);
+        if (M.eval_every != 1 && M.eval_every != 4) return fail(PYFPT_EINVAL, "instance %d: eval_every must be 1 or 4", i);
+        bool ok = std::isfinite(M.out_scale) && std::isfinite(B.target_N);
+        for (int q = 0; q < 3; ++q) ok = ok && std::isfinite(M.in_mean[q]) && std::isfinite(M.in_inv_scale[q]);
+        if (!ok) return fail(PYFPT_EINVAL, "instance %d: learned bias constants must be finite", i);
+        break;
+    }
     default:
         return fail(PYFPT_EINVAL, "instance %d: unknown bias kind %d", i, B.kind);
     }
@@ -227,10 +237,17 @@ int prepare(const pyfpt_instance *ins, int n_inst, Prepared &P) {
                           ? PYFPT_BIAS_NOISE_SCALED : ins[i].bias.kind;
         if (ins[i].pot.kind != P.pot || b != P.bias)
             return fail(PYFPT_EUNSUPPORTED, "all instances of a batch must share potential and bias kinds");
+        if (b == PYFPT_BIAS_MLP && (ins[i].bias.mlp.params != ins[0].bias.mlp.params ||
+                                    ins[i].bias.mlp.eval_every != ins[0].bias.mlp.eval_every))
+            return fail(PYFPT_EUNSUPPORTED, "learned-bias instances of a batch must share the network and eval_every");
         const int ns = ins[i].bins.n_sub ? ins[i].bins.n_sub : kDefaultNsub;
         if (ns != ns0) return fail(PYFPT_EINVAL, "all instances of a batch must share n_sub");
     }
     P.n_sub = static_cast<uint32_t>(ns0);
+    if (P.bias == PYFPT_BIAS_MLP) {
+        P.mlp_params = static_cast<const uint16_t *>(ins[0].bias.mlp.params);
+        P.mlp_every = ins[0].bias.mlp.eval_every;
+    }
     P.inst.resize(n_inst);
     P.mi.resize(n_inst);
     P.rl.resize(n_inst);
@@ -254,6 +271,14 @@ int prepare(const pyfpt_instance *ins, int n_inst, Prepared &P) {
         C.inv_w2 = static_cast<float>(1.0 / (I.pot.w * I.pot.w));
         C.inv_2w2 = static_cast<float>(0.5 / (I.pot.w * I.pot.w));
         C.A = I.bias.kind == PYFPT_BIAS_NONE ? 0.0f : static_cast<float>(I.bias.A);
+        if (I.bias.kind == PYFPT_BIAS_MLP) {
+            for (int q = 0; q < 3; ++q) {
+                D.mlp.in_mean[q] = I.bias.mlp.in_mean[q];
+                D.mlp.in_inv[q] = I.bias.mlp.in_inv_scale[q];
+            }
+            D.mlp.out_scale = I.bias.mlp.out_scale;
+            D.mlp.target_N = static_cast<float>(I.bias.target_N);
+        }
         C.p = I.bias.p;
         C.phi_end = static_cast<float>(I.phi_end);
         C.phi_uv = static_cast<float>(I.phi_uv);
@@ -355,8 +380,9 @@ WsMap ws_map(const Prepared &P, int n_wg) {
 }
 
 void resolve_cfg(const Device &d, const Prepared &P, LaunchCfg &c, bool &lds) {
-    if (c.block <= 0) c.block = 512;
-    if (c.wg_per_cu <= 0) c.wg_per_cu = 2;
+    const bool mlp = P.bias == PYFPT_BIAS_MLP;
+    if (c.block <= 0) c.block = mlp ? 256 : 512;
+    if (c.wg_per_cu <= 0) c.wg_per_cu = mlp ? 1 : 2;
     if (c.chunk <= 0) c.chunk = 1;
     // LDS budget per workgroup: the CU's LDS shared by its resident workgroups
     const size_t budget = std::min<size_t>(d.max_lds, 160 * 1024 / static_cast<size_t>(c.wg_per_cu));
@@ -383,6 +409,8 @@ int run_prepared(Device &d, const Prepared &P, uint64_t seed, const LaunchCfg &c
     resolve_cfg(d, P, cfg, lds);
     if (cfg.block < 64 || cfg.block > 1024 || cfg.block % 64)
         return fail(PYFPT_EINVAL, "block must be a multiple of 64 in 64..1024");
+    if (P.bias == PYFPT_BIAS_MLP && cfg.block > 256)
+        return fail(PYFPT_EINVAL, "the learned bias runs with block <= 256");
     if (cfg.wg_per_cu * cfg.block > 2048) return fail(PYFPT_EINVAL, "wg_per_cu * block must be <= 2048");
     const int n_wg = d.cus * cfg.wg_per_cu;
     const WsMap m = ws_map(P, n_wg);
@@ -425,6 +453,8 @@ int run_prepared(Device &d, const Prepared &P, uint64_t seed, const LaunchCfg &c
     sa.slices = W + m.slices;
     sa.lay = P.lay;
     sa.chunk = static_cast<uint32_t>(cfg.chunk);
+    sa.mlp_params = P.mlp_params;
+    sa.mlp_every = P.mlp_every;
     if (opt && opt->dump.n) {
         if (!opt->dump.k || !opt->dump.lw || !opt->dump.phi || !opt->dump.status || opt->dump.stride == 0)
             return fail(PYFPT_EINVAL, "dump: all four arrays and stride >= 1 are required");
@@ -559,6 +589,7 @@ int autotune(Device &d, const pyfpt_instance *ins, int n_inst, uint64_t seed, hi
     best = LaunchCfg{512, 2, 1};
     std::vector<uint64_t> counts(C.counts_total);
     for (const LaunchCfg &c : cands) {
+        if (P.bias == PYFPT_BIAS_MLP && c.block > 256) continue;
         LaunchCfg cc = c;
         bool lds = false;
         resolve_cfg(d, C, cc, lds);
@@ -714,6 +745,24 @@ int pyfpt_workspace_size(const pyfpt_instance *inst, int32_t n_inst, const pyfpt
     } catch (...) {
         return fail(PYFPT_ENOMEM, "host exception (allocation failure)");
     }
+}
+
+int pyfpt_mlp_forward(const pyfpt_mlp *mlp, double target_N, const float *phi, const float *N, float *r,
+                      uint64_t n, void *stream) {
+    if (!mlp) return fail(PYFPT_EINVAL, "NULL network");
+    if (n == 0) return PYFPT_OK;
+    if (!mlp->params || !phi || !N || !r) return fail(PYFPT_EINVAL, "NULL pointer");
+    if (mlp->hidden != 64) return fail(PYFPT_EINVAL, "hidden must be 64");
+    MlpConsts c{};
+    for (int q = 0; q < 3; ++q) {
+        c.in_mean[q] = mlp->in_mean[q];
+        c.in_inv[q] = mlp->in_inv_scale[q];
+    }
+    c.out_scale = mlp->out_scale;
+    c.target_N = static_cast<float>(target_N);
+    HIP_TRY(launch_mlp_forward(static_cast<const uint16_t *>(mlp->params), c, phi, N, r, n,
+                               static_cast<hipStream_t>(stream)), "launch mlp forward");
+    return PYFPT_OK;
 }
 
 int pyfpt_device_cus(int32_t *cus) {

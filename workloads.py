@@ -63,6 +63,8 @@ class Instance:
     k_max: int = K_MAX_CAP
     stream: int = 0
     edges: np.ndarray = field(default_factory=lambda: np.linspace(0.0, 1.0, 2))
+    mlp: object = None        # MlpParams of the learned bias
+    target_N: float = 0.0     # N* input of the learned bias
 
     def esc(self) -> float:
         if math.isfinite(self.phi_uv):
@@ -163,6 +165,19 @@ def c3(n_traj: int = 1_000_000, n_inst: int = 64, seed: int = 0):
     return out
 
 
+def c4_instance(params, n_traj: int = 1_000_000, target_N: float = 196.0, stream: int = 0) -> Instance:
+    """The learned proposal on the diffusion-dominated case of C2 (m = 1, phi_in = 6, wall at 8),
+    aimed at N* (P(N*) ~ 1e-30 near N* = 196 for this potential)."""
+    base = c2(n_traj)[3]
+    return replace(base, name="C4_mlp", bias=BIAS_MLP, A=0.0, mlp=params, target_N=target_N, stream=stream)
+
+
+def c4_params(seed: int = 0, scale: float = 1.0, out_scale: float = 1.0, eval_every: int = 4) -> "MlpParams":
+    """Network inputs normalised for the C4 case: phi in [sqrt 2, 8], N in [0, 600], N* ~ 200."""
+    return MlpParams.random(seed, scale, in_mean=(5.0, 200.0, 200.0), in_inv_scale=(0.4, 0.005, 0.01),
+                            out_scale=out_scale, eval_every=eval_every)
+
+
 def c5(n_traj: int = 1_000_000_000) -> Instance:
     mu, sig = MU_SIGMA["C5_T"]
     kmax = k_max_rule(mu, 1e-4)
@@ -178,6 +193,51 @@ def paper_diffusion(A: float, n_traj: int = 200_000, stream: int = 0) -> Instanc
     return Instance(f"V2_A{A}", m=1.0, phi_in=phi, phi_uv=phi, bias=BIAS_NOISE_SCALED if A else BIAS_NONE,
                     A=A, dN=1e-3, n_traj=n_traj, k_max=K_MAX_CAP, stream=stream,
                     edges=np.linspace(0.0, 80.0, 161))
+
+
+# ----------------------------------------------------------------------------
+# Learned-proposal network parameters (inputs): 3 -> 64 -> 64 -> 1, tanh, bfloat16.
+# ----------------------------------------------------------------------------
+def bf16_round(x) -> np.ndarray:
+    """Round binary32 values to the nearest bfloat16 (ties to even), kept as binary32."""
+    b = np.ascontiguousarray(x, np.float32).view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32)
+
+
+@dataclass
+class MlpParams:
+    """4481 parameters in the order W1[64][3], b1[64], W2[64][64], b2[64], w3[64], b3, every
+    value a bfloat16 (stored here as binary32), plus the input normalisation and output scale."""
+    values: np.ndarray
+    in_mean: tuple = (0.0, 0.0, 0.0)
+    in_inv_scale: tuple = (1.0, 1.0, 1.0)
+    out_scale: float = 1.0
+    eval_every: int = 4
+
+    N_PARAMS = 4481
+
+    def values_f32(self) -> np.ndarray:
+        return bf16_round(self.values)
+
+    def bf16_bits(self) -> np.ndarray:
+        return (self.values_f32().view(np.uint32) >> 16).astype(np.uint16)
+
+    @staticmethod
+    def random(seed: int = 0, scale: float = 1.0, **kw) -> "MlpParams":
+        """Glorot-uniform weights, zero biases except a small random b3 (seeded numpy)."""
+        rng = np.random.default_rng(seed)
+        v = np.zeros(4481, np.float32)
+        lim1 = scale * np.sqrt(6.0 / (3 + 64))
+        lim2 = scale * np.sqrt(6.0 / (64 + 64))
+        lim3 = scale * np.sqrt(6.0 / (64 + 1))
+        v[0:192] = rng.uniform(-lim1, lim1, 192)
+        v[192:256] = rng.uniform(-0.1, 0.1, 64)
+        v[256:4352] = rng.uniform(-lim2, lim2, 4096)
+        v[4352:4416] = rng.uniform(-0.1, 0.1, 64)
+        v[4416:4480] = rng.uniform(-lim3, lim3, 64)
+        v[4480] = rng.uniform(-0.1, 0.1)
+        return MlpParams(bf16_round(v), **kw)
 
 
 def flat_well(L: float = 1.5, x: float = 1.0, V0: float = 1.0, dN: float = 1e-3, n_traj: int = 100_000,
