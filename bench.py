@@ -33,9 +33,10 @@ PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
 #   Philox 60/4 (two 32x32->64 multiplies and four xors per round, ten rounds per 4 steps)
 #   uniforms 20/4, Box-Muller 72/2 (log 29, -2L 1, sqrt 13, sincos 27, rho*cos/sin 2).
 OPS_PER_STEP = 31 + 15 + 5 + 36
-# HBM bytes per launch of the step kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE (see profiles/),
-# None until taken on the current kernel
-TRAFFIC = None
+# HBM bytes per launch of the step kernel on this workload: rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1
+# (factors read off a plain 1 GiB copy, `--copy-calibration`), summaries under profiles/.
+# Reset to None whenever the step kernel changes until the counters are taken again.
+TRAFFIC = 3.252e9
 
 
 def parse():
@@ -52,7 +53,22 @@ def parse():
     p.add_argument("--wg-per-cu", type=int, default=2)
     p.add_argument("--chunk", type=int, default=1)
     p.add_argument("--autotune", action="store_true")
+    p.add_argument("--copy-calibration", action="store_true",
+                   help="only copy 1 GiB device-to-device 3 times (scale reference for HBM byte counters)")
     return p.parse_args()
+
+
+def copy_calibration():
+    """A plain copy of known size: 1 GiB read + 1 GiB written per launch, for scaling the
+    FETCH_SIZE / WRITE_SIZE counters of the step kernel."""
+    import torch
+    torch.cuda.set_device(0)
+    src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4, "launches": 3}))
 
 
 def cpu_baseline(insts, target_s):
@@ -60,24 +76,23 @@ def cpu_baseline(insts, target_s):
     import numpy as np
     import oracle as O
     to_model = O.Model.from_instance
-    # calibrate on a small prefix, then size the sample to about target_s seconds
+    # per instance, double the prefix of ids until one run of the oracle takes at least a third
+    # of the instance's share of target_s, and keep that run's measurement
     steps = 0
     elapsed = 0.0
     threads = 0
-    per_inst = []
-    for inst in insts:
-        n = 64
-        t0 = time.perf_counter()
-        tr = O.simulate(to_model(inst), 0, n)
-        dt = time.perf_counter() - t0
-        per_inst.append(max(dt / n, 1e-9))
     share = target_s / len(insts)
     sample = []
-    for inst, per in zip(insts, per_inst):
-        n = int(max(64, min(inst.n_traj, share / per)))
-        t0 = time.perf_counter()
-        tr = O.simulate(to_model(inst), 0, n)
-        elapsed += time.perf_counter() - t0
+    for inst in insts:
+        n = 256
+        while True:
+            t0 = time.perf_counter()
+            tr = O.simulate(to_model(inst), 0, n)
+            dt = time.perf_counter() - t0
+            if dt >= share / 3 or n >= inst.n_traj:
+                break
+            n = int(min(inst.n_traj, n * min(8.0, max(2.0, share / max(dt, 1e-3)))))
+        elapsed += dt
         steps += int(tr.k.sum())
         threads = tr.threads
         sample.append(f"{inst.name}:{n}")
@@ -90,6 +105,9 @@ def main():
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
         sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
     import numpy as np
     import torch
     import paper_2206_11234_amd as F
@@ -141,7 +159,7 @@ def main():
                    "steps_per_pass": steps_per_pass},
         "ess_per_s": ess_total / wall,
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
-                     "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": TRAFFIC,
+                     "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": TRAFFIC, "traffic_unit": "bytes/launch",
                      "kernel": "fpt_step_kernel", "kernel_ms": kmean * 1e3,
                      "ops_per_step": OPS_PER_STEP},
     }
