@@ -64,3 +64,19 @@ def test_mlp_sampler_matches_oracle(fpt, every):
     assert np.median(lw_rel) < 3e-4
     assert np.quantile(lw_rel, 0.99) < 3e-3
     assert int(res.count.sum()) == inst.n_traj
+
+
+@pytest.mark.parametrize("every", [4, 1])
+def test_constant_network_sampler_bit_exact(fpt, every):
+    """A network whose only nonzero parameter is b3 gives r = out_scale b3 exactly on the matrix
+    cores (zero weights times bounded activations add exact zeros), so the learned path must
+    reproduce the oracle's noise-scaled bias of that value bit for bit."""
+    from helpers import assert_dump_matches
+    v = np.zeros(W.MlpParams.N_PARAMS, np.float32)
+    v[4480] = 0.5
+    params = W.MlpParams(v, out_scale=2.0, eval_every=every)
+    base = W.c2(2000)[3]                  # A = 1
+    inst = W.c4_instance(params, n_traj=2000, stream=base.stream)
+    res, dump, _ = fpt.run(inst, 0, block=256, wg_per_cu=1, chunk=1, dump_n=inst.n_traj)
+    tr = O.simulate(to_model(base), 0, base.n_traj)
+    assert_dump_matches(dump, tr)
