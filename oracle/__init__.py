@@ -95,6 +95,12 @@ def lib():
                                       ctypes.c_int]
         L.oracle_simulate.restype = ctypes.c_int
         L.oracle_mlp_r_batch.argtypes = [ctypes.POINTER(_Params), f32p, f32p, f64p, ctypes.c_int64]
+        vp = ctypes.c_void_p
+        L.oracle_records.argtypes = [ctypes.POINTER(_Params), u64p, ctypes.c_int64, ctypes.c_int, u64p, vp,
+                                     u64p, f64p, i32p]
+        L.oracle_records.restype = ctypes.c_int64
+        L.oracle_loss_grad.argtypes = [ctypes.POINTER(_Params), f64p, vp, u64p, ctypes.c_int64, f64p,
+                                       ctypes.c_double, f64p, f64p, f64p, f64p]
         _lib = L
     return _lib
 
@@ -193,6 +199,64 @@ def mlp_r(model: Model, phi, N) -> np.ndarray:
     lib().oracle_mlp_r_batch(ctypes.byref(P), _ptr(phi, ctypes.c_float), _ptr(N, ctypes.c_float),
                              _ptr(out, ctypes.c_double), phi.size)
     return out
+
+
+# --------------------------------------------------------------------------
+# Training of the learned proposal: records of paths drawn from a proposal and
+# the loss log M2(theta) with its gradient (see the C source for the derivation).
+# --------------------------------------------------------------------------
+RECORD_DTYPE = np.dtype([("phi", "<f4"), ("k", "<u4"), ("H", "<f4"), ("pn", "<u4")])
+
+
+@dataclass
+class Records:
+    rec: np.ndarray        # RECORD_DTYPE, path i owns rec[off[i]:off[i+1]]
+    off: np.ndarray        # uint64, n_paths + 1
+    k: np.ndarray          # replayed step counts
+    lw: np.ndarray         # replayed ln w under the sampling proposal
+    status: np.ndarray
+
+
+def records(model: Model, seed: int, t_ids, E: int) -> Records:
+    """Replay the paths t_ids under the model's proposal (binary32 mirror) and cut each into
+    records at multiples of E steps."""
+    L = lib()
+    t = np.ascontiguousarray(t_ids, np.uint64)
+    n = t.size
+    P = model.to_c(seed)
+    k = np.zeros(n, np.uint64)
+    lw = np.zeros(n, np.float64)
+    st = np.zeros(n, np.int32)
+    off = np.zeros(n + 1, np.uint64)
+    L.oracle_records(ctypes.byref(P), _ptr(t, ctypes.c_uint64), n, int(E), _ptr(off, ctypes.c_uint64), None,
+                     _ptr(k, ctypes.c_uint64), _ptr(lw, ctypes.c_double), _ptr(st, ctypes.c_int32))
+    off[1:] = np.cumsum((k + np.uint64(E - 1)) // np.uint64(E))
+    rec = np.zeros(int(off[-1]), RECORD_DTYPE)
+    bad = L.oracle_records(ctypes.byref(P), _ptr(t, ctypes.c_uint64), n, int(E), _ptr(off, ctypes.c_uint64),
+                           ctypes.c_void_p(rec.ctypes.data), _ptr(k, ctypes.c_uint64), _ptr(lw, ctypes.c_double),
+                           _ptr(st, ctypes.c_int32))
+    assert bad == 0
+    return Records(rec, off, k, lw, st)
+
+
+def loss_grad(model: Model, theta, recs: Records, lw0, n_total: float):
+    """log M2(theta) over the window paths of `recs`, its gradient (4481) and ln w_theta per
+    path.  model supplies the input normalisation, out_scale, N* and dN."""
+    L = lib()
+    th = np.ascontiguousarray(theta, np.float64)
+    assert th.size == 4481
+    lw0 = np.ascontiguousarray(lw0, np.float64)
+    n = recs.off.size - 1
+    P = model.to_c(0)
+    loss = np.zeros(1)
+    grad = np.zeros(4481)
+    lwt = np.zeros(n)
+    scratch = np.zeros(max(n, 1) * 4481)
+    L.oracle_loss_grad(ctypes.byref(P), _ptr(th, ctypes.c_double), ctypes.c_void_p(recs.rec.ctypes.data),
+                       _ptr(recs.off, ctypes.c_uint64), n, _ptr(lw0, ctypes.c_double), float(n_total),
+                       _ptr(loss, ctypes.c_double), _ptr(grad, ctypes.c_double), _ptr(lwt, ctypes.c_double),
+                       _ptr(scratch, ctypes.c_double))
+    return float(loss[0]), grad, lwt
 
 
 def philox(ctr, key):

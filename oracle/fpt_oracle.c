@@ -598,3 +598,208 @@ void oracle_normals_f64_batch(uint64_t seed, uint32_t stream, uint64_t t, uint32
 {
     for (uint32_t j = 0; j < nj; ++j) oracle_normals_f64(seed, stream, t, j0 + j, out + 4 * (size_t)j);
 }
+
+/* ------------------------------------------------------------------ */
+/* Training of the learned proposal.                                    */
+/*                                                                      */
+/* Sec. 2.2 writes the weight of a path as the ratio of its target and  */
+/* sample densities; Sec. 3.4 leaves the choice of the best bias open.  */
+/* The proposal is tuned by minimising the second moment of the weights */
+/* of the runs that end in a target window B*,                          */
+/*     M2(theta) = E_theta[w_theta^2 1_B*] = E_0[w_0 w_theta 1_B*],      */
+/* estimated on paths drawn once from the current proposal theta_0.    */
+/* On a fixed path the target-measure noise increment of step k is      */
+/* eta_k = r_0,k dN + sqrt(dN) xi_k (the sample-path increment with the */
+/* bias drift taken out), so the weight the same path would have under  */
+/* a candidate bias r_theta is                                         */
+/*     ln w_theta = sum_k [ -r_theta,k eta_k + r_theta,k^2 dN/2 ].       */
+/* The candidate network is held over groups of E steps (its evaluation */
+/* schedule), so a path reduces to records at its evaluation points:    */
+/* the network input (phi, k), H = sum of eta over the group and the    */
+/* group's length n, and ln w_theta = sum_e [-r_e H_e + r_e^2 n_e dN/2]. */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    float phi;      /* field at the evaluation point (before the step)       */
+    uint32_t k;     /* step index of the evaluation point                    */
+    float H;        /* sum over the group of eta = fma(r_0, dN, sqrt(dN) xi) */
+    uint32_t pn;    /* path index << 3 | steps in the group (1 .. 4)         */
+} oracle_record;
+
+/* Replay one path under the model's own proposal (binary32 mirror, identical to simulate_f32)
+ * and cut it into records at multiples of E steps; at most cap records are written. */
+static int64_t records_f32(const oracle_params *P, const consts_f32 *c, uint64_t t, uint32_t path, int E,
+                           oracle_record *rec, int64_t cap, uint64_t *k_out, double *lw_out, int *st_out)
+{
+    float phi = c->phi_in;
+    double lw = 0.0;
+    uint64_t k = 0;
+    float xi4[4];
+    float r_mlp = 0.0f;
+    int status = ST_RUNNING;
+    int64_t n_rec = 0;
+    float H = 0.0f, phi_e = phi;
+    uint32_t k_e = 0, n_e = 0;
+    while (status == ST_RUNNING) {
+        if ((k & 3u) == 0) oracle_normals_f32(P->seed, P->stream, t, (uint32_t)(k >> 2), xi4);
+        if (k % (uint64_t)E == 0) {
+            phi_e = phi;
+            k_e = (uint32_t)k;
+            H = 0.0f;
+            n_e = 0;
+        }
+        float xi = xi4[k & 3u];
+        float D, S;
+        drift_noise_f32(P, c, phi, &D, &S);
+        float r;
+        if (P->bias_kind == BIAS_MLP) {
+            if (P->eval_every == 1 || (k & 3u) == 0) r_mlp = (float)oracle_mlp_r(P, phi, (float)k * c->dN);
+            r = r_mlp;
+        } else {
+            r = bias_ratio_f32(P, c, phi, S);
+        }
+        float B = r * S;
+        float drift = D + B;
+        float det = fmaf(drift, c->dN, phi);
+        float amp = S * c->sq;
+        float nphi = fmaf(amp, xi, det);
+        float sxi = c->sq * xi;
+        float inc = fmaf(r, c->hdN, sxi);
+        float dlw = -(r * inc);
+        lw += (double)dlw;
+        H = H + fmaf(r, c->dN, sxi);
+        n_e += 1;
+        if (nphi > c->phi_uv) nphi = c->two_uv - nphi;
+        phi = nphi;
+        k += 1;
+        if (phi <= c->phi_end) status = ST_ENDED;
+        else if (k >= P->k_max) status = ST_CENSORED;
+        else if (phi > c->phi_esc) status = ST_ESCAPED;
+        if (k % (uint64_t)E == 0 || status != ST_RUNNING) {
+            if (n_rec < cap) {
+                rec[n_rec].phi = phi_e;
+                rec[n_rec].k = k_e;
+                rec[n_rec].H = H;
+                rec[n_rec].pn = (path << 3) | n_e;
+            }
+            n_rec += 1;
+        }
+    }
+    *k_out = k;
+    *lw_out = lw;
+    *st_out = status;
+    return n_rec;
+}
+
+/* Records of the paths t_ids[0..n): path i owns rec[rec_off[i] .. rec_off[i+1]).  Returns the
+ * number of paths whose record count did not match their slot (0 when the offsets came from
+ * the same paths' step counts). */
+int64_t oracle_records(const oracle_params *P, const uint64_t *t_ids, int64_t n, int E, const uint64_t *rec_off,
+                       oracle_record *rec, uint64_t *k_out, double *lw_out, int32_t *st_out)
+{
+    consts_f32 c;
+    make_consts_f32(P, &c);
+    int64_t bad = 0;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 4) reduction(+ : bad)
+#endif
+    for (int64_t i = 0; i < n; ++i) {
+        int st;
+        const int64_t cap = (int64_t)(rec_off[i + 1] - rec_off[i]);
+        const int64_t got = records_f32(P, &c, t_ids[i], (uint32_t)i, E, rec + rec_off[i], cap, &k_out[i],
+                                        &lw_out[i], &st);
+        st_out[i] = st;
+        if (got != cap) bad += 1;
+    }
+    return bad;
+}
+
+/* The network being trained, in binary64 without roundings (its parameters theta are the
+ * binary32 master copy; inference rounds them and the activations to bfloat16). */
+static double net_f64(const oracle_params *P, const double *th, float phi, uint32_t k, float dN_f, double x[3],
+                      double h1[64], double h2[64])
+{
+    const double *W1 = th, *b1 = th + 192, *W2 = th + 256, *b2 = th + 4352, *w3 = th + 4416, b3 = th[4480];
+    const float N = (float)k * dN_f;
+    x[0] = ((double)phi - (double)P->in_mean[0]) * (double)P->in_inv[0];
+    x[1] = ((double)N - (double)P->in_mean[1]) * (double)P->in_inv[1];
+    x[2] = ((double)(float)P->target_N - (double)P->in_mean[2]) * (double)P->in_inv[2];
+    for (int u = 0; u < 64; ++u) {
+        double a = b1[u];
+        for (int s = 0; s < 3; ++s) a += W1[u * 3 + s] * x[s];
+        h1[u] = tanh(a);
+    }
+    double o = b3;
+    for (int u = 0; u < 64; ++u) {
+        double a = b2[u];
+        for (int v = 0; v < 64; ++v) a += W2[u * 64 + v] * h1[v];
+        h2[u] = tanh(a);
+        o += w3[u] * h2[u];
+    }
+    return (double)P->out_scale * o;
+}
+
+/* Loss log M2(theta) = log( sum_{i in B*} w_0,i w_theta,i / n_total ) over the window paths
+ * given by their records and sampled weights lw0, and its gradient with respect to the 4481
+ * parameters:
+ *   d log M2 / d theta = sum_i c_i sum_e (r_e n_e dN - H_e) d r_e / d theta,
+ *   c_i = w_0,i w_theta,i / sum_j w_0,j w_theta,j.
+ * grad_path (n_paths x 4481 scratch) keeps the per-path sums so the total is summed in path
+ * order. */
+void oracle_loss_grad(const oracle_params *P, const double *theta, const oracle_record *rec, const uint64_t *rec_off,
+                      int64_t n_paths, const double *lw0, double n_total, double *loss, double *grad,
+                      double *lw_theta, double *grad_path)
+{
+    const float dN_f = (float)P->dN;
+    const double dN = (double)dN_f;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t i = 0; i < n_paths; ++i) {
+        double x[3], h1[64], h2[64], s = 0.0;
+        for (uint64_t e = rec_off[i]; e < rec_off[i + 1]; ++e) {
+            const double r = net_f64(P, theta, rec[e].phi, rec[e].k, dN_f, x, h1, h2);
+            const double n = (double)(rec[e].pn & 7u);
+            s += -r * (double)rec[e].H + r * r * n * dN * 0.5;
+        }
+        lw_theta[i] = s;
+    }
+    double M = -INFINITY;
+    for (int64_t i = 0; i < n_paths; ++i) M = fmax(M, lw0[i] + lw_theta[i]);
+    double S = 0.0;
+    for (int64_t i = 0; i < n_paths; ++i) S += exp(lw0[i] + lw_theta[i] - M);
+    *loss = M + log(S) - log(n_total);
+    const double *W2 = theta + 256, *w3 = theta + 4416;
+    const double osc = (double)P->out_scale;
+#ifdef _OPENMP
+#pragma omp parallel for schedule(dynamic, 1)
+#endif
+    for (int64_t i = 0; i < n_paths; ++i) {
+        double *g = grad_path + (size_t)i * 4481;
+        for (int j = 0; j < 4481; ++j) g[j] = 0.0;
+        const double ci = exp(lw0[i] + lw_theta[i] - M) / S;
+        double x[3], h1[64], h2[64], d2[64];
+        for (uint64_t e = rec_off[i]; e < rec_off[i + 1]; ++e) {
+            const double r = net_f64(P, theta, rec[e].phi, rec[e].k, dN_f, x, h1, h2);
+            const double n = (double)(rec[e].pn & 7u);
+            const double go = ci * (r * n * dN - (double)rec[e].H) * osc;   /* d loss / d o, o = w3.h2 + b3 */
+            g[4480] += go;
+            for (int u = 0; u < 64; ++u) {
+                g[4416 + u] += go * h2[u];
+                d2[u] = go * w3[u] * (1.0 - h2[u] * h2[u]);
+                g[4352 + u] += d2[u];
+            }
+            for (int u = 0; u < 64; ++u)
+                for (int v = 0; v < 64; ++v) g[256 + u * 64 + v] += d2[u] * h1[v];
+            for (int v = 0; v < 64; ++v) {
+                double a = 0.0;
+                for (int u = 0; u < 64; ++u) a += W2[u * 64 + v] * d2[u];
+                const double d1 = a * (1.0 - h1[v] * h1[v]);
+                g[192 + v] += d1;
+                for (int s = 0; s < 3; ++s) g[v * 3 + s] += d1 * x[s];
+            }
+        }
+    }
+    for (int j = 0; j < 4481; ++j) grad[j] = 0.0;
+    for (int64_t i = 0; i < n_paths; ++i)
+        for (int j = 0; j < 4481; ++j) grad[j] += grad_path[(size_t)i * 4481 + j];
+}
