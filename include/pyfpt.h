@@ -238,6 +238,82 @@ int pyfpt_workspace_size(const pyfpt_instance *inst, int32_t n_inst, const pyfpt
 int pyfpt_mlp_forward(const pyfpt_mlp *mlp, double target_N, const float *phi, const float *N, float *r,
                       uint64_t n, void *stream);
 
+/* ---- training of the learned proposal ----
+ *
+ * The paper leaves the choice of the best bias open (Sec. 3.4).  The learned proposal is
+ * tuned to minimise the second moment of the weights of the runs that end in a target window
+ * B* = (lo, hi] of N:
+ *     log M2(theta) = log( sum_{i in B*} w_0,i w_theta,i / n_total ),
+ * over runs i drawn once from the current proposal theta_0 (weights w_0, Sec. 2.2), where
+ * w_theta,i is the weight the same path would have under the candidate network theta.  With
+ * eta_k = r_0,k dN + sqrt(dN) xi_k, the noise increment of step k under the target process,
+ * ln w_theta = sum_k [ -r_theta,k eta_k + r_theta,k^2 dN/2 ].  The candidate is held over
+ * groups of `group` (1 or 4) steps, so each path reduces to one record per group.
+ */
+typedef struct pyfpt_record {
+    float phi;                       /* field before the group's first step */
+    uint32_t k;                      /* step index of the group's first step */
+    float H;                         /* sum over the group of fma(r_0, dN, sqrt(dN) xi), binary32 in step order */
+    uint32_t path_n;                 /* path index << 3 | number of steps in the group (1..4) */
+} pyfpt_record;
+
+/*
+ * Replay the runs t_ids[0..n_paths) of a sampling run (same instance, same seed) under the
+ * instance's proposal, with the sampler's own arithmetic, and cut them into records: path i
+ * writes rec[rec_off[i] .. rec_off[i+1]), which must be its ceil(k_i / group) records.  All
+ * arrays are host memory; k_out, lw_out and status_out receive the replayed run (identical to
+ * the sampled one), so a caller can check the slots.  EINVAL: group not 1 or 4, rec_off not
+ * ascending, or the instance as in pyfpt_run.  The call synchronises.
+ */
+int pyfpt_proposal_records(const pyfpt_instance *inst, uint64_t seed, const uint64_t *t_ids, int32_t n_paths,
+                           int32_t group, const uint64_t *rec_off, pyfpt_record *rec, uint32_t *k_out,
+                           double *lw_out, int32_t *status_out, const pyfpt_options *opt);
+
+/*
+ * log M2(theta) and its gradient from records (host arrays): theta holds the 4481 binary32
+ * master parameters in the order of pyfpt_mlp; net supplies the input normalisation and
+ * out_scale (its params are not read); dN as in the sampling run; lw0[i] = ln w_0 of path i;
+ * n_total = number of runs drawn.  Outputs: *loss, grad[4481] (binary64), lw_theta[n_paths].
+ * The network is evaluated in binary32 without roundings (the training copy); the gradient is
+ * summed in a fixed order.  EINVAL: n_paths < 1, rec_off not ascending to n_rec, a record's
+ * path index >= n_paths or its step count outside 1..4.  The call synchronises.
+ */
+int pyfpt_proposal_loss_grad(const pyfpt_mlp *net, double target_N, double dN, const float *theta,
+                             const pyfpt_record *rec, uint64_t n_rec, const uint64_t *rec_off, int32_t n_paths,
+                             const double *lw0, double n_total, double *loss, double *grad, double *lw_theta,
+                             const pyfpt_options *opt);
+
+typedef struct pyfpt_train_config {
+    double window_lo, window_hi;     /* target window B* = (lo, hi] in N */
+    uint64_t n_sample;               /* runs drawn per round from the current proposal */
+    int32_t max_paths;               /* window runs kept per round (0 = all) */
+    int32_t rounds;                  /* sampling rounds */
+    int32_t steps;                   /* Adam steps per round */
+    int32_t group;                   /* 1 or 4: the network's evaluation interval */
+    float lr, beta1, beta2, eps;     /* Adam */
+} pyfpt_train_config;
+
+typedef struct pyfpt_train_report {
+    int32_t n_window;                /* runs of the round that ended in the window */
+    int32_t n_used;                  /* of which used for training */
+    uint64_t n_records;
+    double loss_first, loss_last;    /* log M2 at the round's first and last Adam step */
+    double kish_window;              /* sum w_0 over the used window runs squared / sum w_0^2 */
+    float ms_sample, ms_records, ms_optimise;
+} pyfpt_train_report;
+
+/*
+ * Train the learned proposal of `inst` (bias.kind = PYFPT_BIAS_MLP; its normalisation,
+ * out_scale, eval_every and target_N are used, its params are not): each round draws
+ * cfg->n_sample runs from the current network (seed + round), keeps the runs that ended in the
+ * window, replays them into records and takes cfg->steps Adam steps on log M2.  theta (host,
+ * 4481 binary32) is the starting master copy on entry and the trained one on return;
+ * params_bf16 (host, 4481) receives the bfloat16 copy for pyfpt_run.  report has cfg->rounds
+ * entries.  EINVAL for a bad configuration.  The call synchronises.
+ */
+int pyfpt_train_proposal(const pyfpt_instance *inst, uint64_t seed, const pyfpt_train_config *cfg, float *theta,
+                         uint16_t *params_bf16, pyfpt_train_report *report, const pyfpt_options *opt);
+
 /* Number of compute units of the current device (0 if none). */
 int pyfpt_device_cus(int32_t *cus);
 

@@ -72,9 +72,27 @@ class pyfpt_options(ctypes.Structure):
                 ("timing_ms", ctypes.POINTER(ctypes.c_float))]
 
 
+class pyfpt_record(ctypes.Structure):
+    _fields_ = [("phi", ctypes.c_float), ("k", ctypes.c_uint32), ("H", ctypes.c_float), ("path_n", ctypes.c_uint32)]
+
+
+class pyfpt_train_config(ctypes.Structure):
+    _fields_ = [("window_lo", ctypes.c_double), ("window_hi", ctypes.c_double), ("n_sample", ctypes.c_uint64),
+                ("max_paths", ctypes.c_int32), ("rounds", ctypes.c_int32), ("steps", ctypes.c_int32),
+                ("group", ctypes.c_int32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
+                ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
+
+
+class pyfpt_train_report(ctypes.Structure):
+    _fields_ = [("n_window", ctypes.c_int32), ("n_used", ctypes.c_int32), ("n_records", ctypes.c_uint64),
+                ("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double), ("kish_window", ctypes.c_double),
+                ("ms_sample", ctypes.c_float), ("ms_records", ctypes.c_float), ("ms_optimise", ctypes.c_float)]
+
+
 # every entry point declared in include/pyfpt.h
 EXPORTS = ("pyfpt_result_layout", "pyfpt_run", "pyfpt_run_batch", "pyfpt_workspace_size",
-           "pyfpt_mlp_forward", "pyfpt_device_cus", "pyfpt_last_error")
+           "pyfpt_mlp_forward", "pyfpt_proposal_records", "pyfpt_proposal_loss_grad", "pyfpt_train_proposal",
+           "pyfpt_device_cus", "pyfpt_last_error")
 
 _lib = None
 
@@ -104,6 +122,13 @@ def load() -> ctypes.CDLL:
     L.pyfpt_device_cus.argtypes = [P(ctypes.c_int32)]
     L.pyfpt_mlp_forward.argtypes = [P(pyfpt_mlp), ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
+    vp = ctypes.c_void_p
+    L.pyfpt_proposal_records.argtypes = [P(pyfpt_instance), ctypes.c_uint64, vp, ctypes.c_int32, ctypes.c_int32, vp, vp,
+                                         vp, vp, vp, P(pyfpt_options)]
+    L.pyfpt_proposal_loss_grad.argtypes = [P(pyfpt_mlp), ctypes.c_double, ctypes.c_double, vp, vp, ctypes.c_uint64, vp,
+                                           ctypes.c_int32, vp, ctypes.c_double, vp, vp, vp, P(pyfpt_options)]
+    L.pyfpt_train_proposal.argtypes = [P(pyfpt_instance), ctypes.c_uint64, P(pyfpt_train_config), vp, vp, vp,
+                                       P(pyfpt_options)]
     L.pyfpt_last_error.restype = ctypes.c_char_p
     for name in EXPORTS:
         getattr(L, name).restype = ctypes.c_int if name != "pyfpt_last_error" else ctypes.c_char_p

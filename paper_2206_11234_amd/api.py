@@ -298,3 +298,85 @@ def device_cus() -> int:
     n = ctypes.c_int32(0)
     L.check(L.load().pyfpt_device_cus(ctypes.byref(n)))
     return int(n.value)
+
+
+# ---------------------------------------------------------------------------
+# training of the learned proposal
+# ---------------------------------------------------------------------------
+RECORD_DTYPE = np.dtype([("phi", "<f4"), ("k", "<u4"), ("H", "<f4"), ("pn", "<u4")])
+
+
+@dataclass
+class Records:
+    rec: np.ndarray         # RECORD_DTYPE; path i owns rec[off[i]:off[i+1]]
+    off: np.ndarray         # uint64, n_paths + 1
+    k: np.ndarray           # replayed step counts
+    lw: np.ndarray          # replayed ln w
+    status: np.ndarray
+
+
+def _ptr(a):
+    return ctypes.c_void_p(a.ctypes.data)
+
+
+def proposal_records(inst, seed: int, t_ids, k, group: int) -> Records:
+    """Replay the runs t_ids (whose step counts k are known from a dump) under the instance's
+    proposal and cut them into records (pyfpt_proposal_records)."""
+    _torch()
+    keep: list = [{}]
+    I = make_instance(inst, 16, keep)
+    t = np.ascontiguousarray(t_ids, np.uint64)
+    k = np.asarray(k, np.uint64)
+    off = np.zeros(t.size + 1, np.uint64)
+    off[1:] = np.cumsum((k + np.uint64(group - 1)) // np.uint64(group))
+    rec = np.zeros(int(off[-1]), RECORD_DTYPE)
+    k_out = np.zeros(t.size, np.uint32)
+    lw_out = np.zeros(t.size, np.float64)
+    st_out = np.zeros(t.size, np.int32)
+    opt = L.pyfpt_options()
+    opt.stream = ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+    L.check(L.load().pyfpt_proposal_records(ctypes.byref(I), int(seed), _ptr(t), t.size, int(group), _ptr(off),
+                                            _ptr(rec), _ptr(k_out), _ptr(lw_out), _ptr(st_out), ctypes.byref(opt)))
+    return Records(rec, off, k_out.astype(np.uint64), lw_out, st_out)
+
+
+def proposal_loss_grad(params, target_N: float, dN: float, theta, recs: Records, lw0, n_total: float):
+    """log M2(theta), its gradient (4481, binary64) and ln w_theta per path, from records."""
+    _torch()
+    keep: list = []
+    m = mlp_struct(params, keep)
+    th = np.ascontiguousarray(theta, np.float32)
+    assert th.size == 4481
+    lw0 = np.ascontiguousarray(lw0, np.float64)
+    n = recs.off.size - 1
+    loss = np.zeros(1)
+    grad = np.zeros(4481)
+    lwt = np.zeros(n)
+    rec = np.ascontiguousarray(recs.rec)
+    off = np.ascontiguousarray(recs.off, np.uint64)
+    opt = L.pyfpt_options()
+    opt.stream = ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+    L.check(L.load().pyfpt_proposal_loss_grad(ctypes.byref(m), float(target_N), float(dN), _ptr(th), _ptr(rec),
+                                              rec.size, _ptr(off), n, _ptr(lw0), float(n_total), _ptr(loss),
+                                              _ptr(grad), _ptr(lwt), ctypes.byref(opt)))
+    return float(loss[0]), grad, lwt
+
+
+def train_proposal(inst, seed: int, theta, *, window, n_sample: int, rounds: int, steps: int, max_paths: int = 0,
+                   lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+    """Train the learned proposal of `inst` (pyfpt_train_proposal).  Returns (theta, bf16 bits,
+    list of per-round report dicts)."""
+    _torch()
+    keep: list = [{}]
+    I = make_instance(inst, 16, keep)
+    th = np.ascontiguousarray(theta, np.float32).copy()
+    bf = np.zeros(4481, np.uint16)
+    cfg = L.pyfpt_train_config(float(window[0]), float(window[1]), int(n_sample), int(max_paths), int(rounds),
+                               int(steps), int(inst.mlp.eval_every), float(lr), float(beta1), float(beta2), float(eps))
+    rep = (L.pyfpt_train_report * rounds)()
+    opt = L.pyfpt_options()
+    opt.stream = ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+    L.check(L.load().pyfpt_train_proposal(ctypes.byref(I), int(seed), ctypes.byref(cfg), _ptr(th), _ptr(bf),
+                                          ctypes.cast(rep, ctypes.c_void_p), ctypes.byref(opt)))
+    reports = [{f: getattr(r, f) for f, _ in L.pyfpt_train_report._fields_} for r in rep]
+    return th, bf, reports

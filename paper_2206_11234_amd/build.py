@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpyfpt.so")
-SOURCES = ["fpt_kernels.hip", "pyfpt_host.hip"]
+SOURCES = ["fpt_kernels.hip", "fpt_train.hip", "pyfpt_host.hip"]
 ARCH = os.environ.get("PYFPT_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

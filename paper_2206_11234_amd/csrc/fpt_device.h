@@ -250,4 +250,41 @@ __device__ __forceinline__ float bias_ratio(const StepConsts &C, float phi, floa
     }
 }
 
+// One Euler-Maruyama step of the biased Langevin equation (Sec. 2.2 eq. eq_euler_maruyam_modified,
+// drift, noise and bias at the pre-step point), the weight increment
+// -r (r dN/2 + sqrt(dN) xi) accumulated in binary64, reflection above phi_UV, and the end /
+// cap / escape tests (Sec. 2.1, Sec. 3).  r_net is the bias when it comes from the learned
+// network.  Returns r and writes sqrt(dN) xi, which the training replay reuses.
+template <int POT, int BIAS>
+__device__ __forceinline__ float em_step(const StepConsts &C, float &phi, uint32_t &k, double &lw, int &st, float xi,
+                                         float r_net, float &sxi) {
+    float D, S;
+    drift_noise<POT>(C, phi, D, S);
+    float drift, r = 0.0f;
+    if constexpr (BIAS == BIAS_NONE) {
+        drift = D;
+    } else {
+        if constexpr (BIAS == BIAS_MLP) r = r_net;
+        else r = bias_ratio<BIAS>(C, phi, S);
+        const float B = r * S;
+        drift = D + B;
+    }
+    const float det = __builtin_fmaf(drift, C.dN, phi);
+    const float amp = S * C.sq;
+    float nphi = __builtin_fmaf(amp, xi, det);
+    sxi = C.sq * xi;
+    if constexpr (BIAS != BIAS_NONE) {
+        const float inc = __builtin_fmaf(r, C.hdN, sxi);
+        const float dlw = -(r * inc);
+        lw += static_cast<double>(dlw);
+    }
+    nphi = (nphi > C.phi_uv) ? C.two_uv - nphi : nphi;
+    phi = nphi;
+    k += 1;
+    const int st_esc = (phi > C.phi_esc) ? ST_ESCAPED : ST_RUNNING;
+    const int st_cap = (k >= C.k_max) ? ST_CENSORED : st_esc;
+    st = (phi <= C.phi_end) ? ST_ENDED : st_cap;
+    return r;
+}
+
 }  // namespace fpt

@@ -227,40 +227,15 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
         if (!__any(active)) break;
 
         // ---- four Euler-Maruyama steps from one Philox call
-        auto em_step = [&](float xi, float r_net) {
-            float D, S;
-            drift_noise<POT>(C, phi, D, S);
-            float drift, r = 0.0f;
-            if constexpr (BIAS == BIAS_NONE) {
-                drift = D;
-            } else {
-                if constexpr (BIAS == BIAS_MLP) r = r_net;
-                else r = bias_ratio<BIAS>(C, phi, S);
-                const float B = r * S;
-                drift = D + B;
-            }
-            const float det = __builtin_fmaf(drift, C.dN, phi);
-            const float amp = S * C.sq;
-            float nphi = __builtin_fmaf(amp, xi, det);
-            if constexpr (BIAS != BIAS_NONE) {
-                const float inc = __builtin_fmaf(r, C.hdN, C.sq * xi);
-                const float dlw = -(r * inc);
-                lw += static_cast<double>(dlw);
-            }
-            nphi = (nphi > C.phi_uv) ? C.two_uv - nphi : nphi;
-            phi = nphi;
-            k += 1;
-            const int st_esc = (phi > C.phi_esc) ? ST_ESCAPED : ST_RUNNING;
-            const int st_cap = (k >= C.k_max) ? ST_CENSORED : st_esc;
-            st = (phi <= C.phi_end) ? ST_ENDED : st_cap;
-        };
+        float sxi;
+        auto step = [&](float xi, float r_net) { (void)em_step<POT, BIAS>(C, phi, k, lw, st, xi, r_net, sxi); };
         if constexpr (BIAS != BIAS_MLP) {
             if (active) {
                 const F4 z = normals4(k >> 2, t, stream, a.key0, a.key1);
                 const float zs[4] = {z.a, z.b, z.c, z.d};
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    if (st == ST_RUNNING) em_step(zs[s], 0.0f);
+                    if (st == ST_RUNNING) step(zs[s], 0.0f);
                 }
             }
         } else {
@@ -272,7 +247,7 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 if (s > 0 && a.mlp_every == 1) r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
-                if (active && st == ST_RUNNING) em_step(zs[s], r_mlp);
+                if (active && st == ST_RUNNING) step(zs[s], r_mlp);
             }
         }
 

@@ -1,0 +1,438 @@
+// fpt_train.hip -- training kernels of the learned proposal.
+//
+// The paper leaves the choice of the best bias open (Sec. 3.4); the learned proposal is trained
+// to minimise the second moment of the importance weights of runs that end in a target window
+// B*:  M2(theta) = E_0[w_0 w_theta 1_B*], estimated on paths drawn once from the current
+// proposal theta_0 (Sec. 2.2: the weight is the ratio of the target and sample path densities).
+// On a fixed path, step k's target-measure noise increment is eta_k = r_0,k dN + sqrt(dN) xi_k,
+// and the weight the same path would have under a candidate bias held over groups of E steps
+// is  ln w_theta = sum_e [ -r_theta(x_e) H_e + r_theta(x_e)^2 n_e dN/2 ],  H_e = sum of eta over
+// group e, n_e its length.  So a path reduces to records (phi_e, k_e, H_e, n_e):
+//
+//   fpt_record_kernel    replays paths under theta_0 (the sampler's own step and network code,
+//                        so the replay reproduces the sampled runs) and writes their records;
+//   fpt_train_fwd_kernel r_theta per record (binary32 network on the master weights), per-path
+//                        sum of ln w_theta in binary64 (one workgroup per path, fixed order);
+//   fpt_train_softmax_kernel  c_i = w_0,i w_theta,i / sum_j w_0,j w_theta,j and log M2;
+//   fpt_train_bwd_kernel gradient of log M2: per record the coefficient
+//                        c_i (r n dN - H) out_scale multiplies d(w3.h2 + b3)/d theta; each lane
+//                        back-propagates one record, and the weight gradient of the 64x64 layer,
+//                        a contraction over the 64 records of a wave, runs on
+//                        v_mfma_f32_32x32x2f32 from LDS tiles;
+//   fpt_train_reduce_kernel  per-workgroup partial gradients summed in a fixed order (binary64);
+//   fpt_adam_kernel      Adam (Kingma & Ba) on the binary32 master weights, then the bfloat16
+//                        copy that the sampler reads.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "fpt_kernels.h"
+#include "fpt_train.h"
+
+namespace fpt {
+
+// ---------------------------------------------------------------------------
+// replay into records
+// ---------------------------------------------------------------------------
+template <int POT, int BIAS>
+__global__ __launch_bounds__(256) void fpt_record_kernel(RecordArgs a) {
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    const bool have = i < a.n_paths;
+    const StepConsts C = a.inst.c;
+    MlpTiles tiles;
+    if constexpr (BIAS == BIAS_MLP) mlp_load_tiles(a.mlp_params, tiles);
+    const MlpConsts mc = a.inst.mlp;
+    const uint64_t t = have ? a.t_ids[i] : 0;
+    const uint64_t base = have ? a.rec_off[i] : 0;
+    const uint64_t cap = have ? a.rec_off[i + 1] - base : 0;
+    const uint32_t emask = static_cast<uint32_t>(a.group - 1);
+    float phi = C.phi_in;
+    uint32_t k = 0;
+    double lw = 0.0;
+    int st = have ? ST_RUNNING : ST_ENDED;
+    float H = 0.0f, phi_e = phi;
+    uint32_t k_e = 0, n_e = 0;
+    uint64_t n_rec = 0;
+    while (__any(st == ST_RUNNING)) {
+        float r_mlp = 0.0f;
+        if constexpr (BIAS == BIAS_MLP) r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
+        F4 z{};
+        if (st == ST_RUNNING) z = normals4(k >> 2, t, a.inst.stream, a.key0, a.key1);
+        const float zs[4] = {z.a, z.b, z.c, z.d};
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            if constexpr (BIAS == BIAS_MLP) {
+                if (s > 0 && a.mlp_every == 1) r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
+            }
+            if (st == ST_RUNNING) {
+                if ((k & emask) == 0) {
+                    phi_e = phi;
+                    k_e = k;
+                    H = 0.0f;
+                    n_e = 0;
+                }
+                float sxi;
+                const float r = em_step<POT, BIAS>(C, phi, k, lw, st, zs[s], r_mlp, sxi);
+                H = H + __builtin_fmaf(r, C.dN, sxi);
+                n_e += 1;
+                if ((k & emask) == 0 || st != ST_RUNNING) {
+                    if (n_rec < cap) {
+                        TrainRec R;
+                        R.phi = phi_e;
+                        R.k = k_e;
+                        R.H = H;
+                        R.pn = (i << 3) | n_e;
+                        a.rec[base + n_rec] = R;
+                    }
+                    n_rec += 1;
+                }
+            }
+        }
+    }
+    if (have) {
+        a.k_out[i] = k;
+        a.lw_out[i] = lw;
+        a.st_out[i] = st;
+        a.n_rec_out[i] = n_rec;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the network being trained (binary32, master weights, no roundings)
+// ---------------------------------------------------------------------------
+// The weights are loop-invariant in the record loops; reading them through a pointer offset
+// by a zero the compiler cannot see through keeps it from hoisting thousands of them out of
+// the loop into registers (they stay uniform, scalar loads).
+__device__ __forceinline__ int opaque_zero() {
+    int z = 0;
+    asm volatile("" : "+s"(z));
+    return z;
+}
+
+__device__ __forceinline__ void net_inputs(const MlpConsts &M, float phi, uint32_t k, float dN, float x[3]) {
+    const float N = static_cast<float>(k) * dN;
+    x[0] = (phi - M.in_mean[0]) * M.in_inv[0];
+    x[1] = (N - M.in_mean[1]) * M.in_inv[1];
+    x[2] = (M.target_N - M.in_mean[2]) * M.in_inv[2];
+}
+
+__device__ __forceinline__ void net_layer1(const float *__restrict__ th, const float x[3], float h1[64]) {
+#pragma unroll
+    for (int u = 0; u < 64; ++u) {
+        float s = th[NET_B1 + u];
+        s = __builtin_fmaf(th[NET_W1 + 3 * u + 0], x[0], s);
+        s = __builtin_fmaf(th[NET_W1 + 3 * u + 1], x[1], s);
+        s = __builtin_fmaf(th[NET_W1 + 3 * u + 2], x[2], s);
+        h1[u] = tanh_hw(s);
+    }
+}
+
+__device__ __forceinline__ float net_unit2(const float *__restrict__ th, int u, const float h1[64]) {
+    float s = th[NET_B2 + u];
+#pragma unroll
+    for (int v = 0; v < 64; ++v) s = __builtin_fmaf(th[NET_W2 + 64 * u + v], h1[v], s);
+    return tanh_hw(s);
+}
+
+// ---------------------------------------------------------------------------
+// forward: r per record, ln w_theta per path
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void fpt_train_fwd_kernel(TrainArgs a, const float *__restrict__ th0) {
+    __shared__ double red[256];
+    const int i = blockIdx.x;
+    const uint64_t e0 = a.rec_off[i], e1 = a.rec_off[i + 1];
+    const double hdN = 0.5 * static_cast<double>(a.dN);
+    double s = 0.0;
+    for (uint64_t b = e0; b < e1; b += blockDim.x) {
+        const uint64_t e = b + threadIdx.x;
+        if (e >= e1) break;
+        const float *th = th0 + opaque_zero();
+        const TrainRec R = a.rec[e];
+        float x[3], h1[64];
+        net_inputs(a.mc, R.phi, R.k, a.dN, x);
+        net_layer1(th, x, h1);
+        float o = 0.0f;
+#pragma unroll 1
+        for (int u = 0; u < 64; ++u) o = __builtin_fmaf(th[NET_W3 + u], net_unit2(th, u, h1), o);
+        const float r = a.mc.out_scale * (o + th0[NET_B3]);
+        a.r_buf[e] = r;
+        const double rd = static_cast<double>(r);
+        const double n = static_cast<double>(R.pn & 7u);
+        s += -rd * static_cast<double>(R.H) + rd * rd * n * hdN;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int w = 128; w > 0; w >>= 1) {
+        if (static_cast<int>(threadIdx.x) < w) red[threadIdx.x] += red[threadIdx.x + w];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) a.lw_theta[i] = red[0];
+}
+
+// ---------------------------------------------------------------------------
+// softmax over paths and log M2
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(1024) void fpt_train_softmax_kernel(TrainArgs a) {
+    __shared__ double red[1024];
+    const int tid = threadIdx.x;
+    double m = -INFINITY;
+    for (int i = tid; i < a.n_paths; i += 1024) m = fmax(m, a.lw0[i] + a.lw_theta[i]);
+    red[tid] = m;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (tid < w) red[tid] = fmax(red[tid], red[tid + w]);
+        __syncthreads();
+    }
+    const double M = red[0];
+    __syncthreads();
+    double s = 0.0;
+    for (int i = tid; i < a.n_paths; i += 1024) s += exp(a.lw0[i] + a.lw_theta[i] - M);
+    red[tid] = s;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    const double S = red[0];
+    for (int i = tid; i < a.n_paths; i += 1024) a.c[i] = exp(a.lw0[i] + a.lw_theta[i] - M) / S;
+    if (tid == 0) a.loss[0] = M + log(S) - log(a.n_total);
+}
+
+// ---------------------------------------------------------------------------
+// backward: one wave per workgroup, 64 records per tile
+// ---------------------------------------------------------------------------
+constexpr int TS = 65;  // padded row stride of the [sample][unit] LDS tiles
+
+typedef float f32x16v __attribute__((ext_vector_type(16)));
+
+__global__ __launch_bounds__(64) void fpt_train_bwd_kernel(TrainArgs a, const float *__restrict__ th0) {
+    __shared__ float HA[64 * TS];   // h1   [sample][unit]
+    __shared__ float HB[64 * TS];   // h2, then delta1
+    __shared__ float HC[64 * TS];   // delta2
+    __shared__ float XS[64 * 4];
+    __shared__ float GS[64];
+    const int lane = threadIdx.x;
+    const double dNd = static_cast<double>(a.dN);
+    f32x16v acc[2][2];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) acc[mb][nb][q] = 0.0f;
+    float g_w3 = 0.0f, g_b2 = 0.0f, g_b1 = 0.0f, g_w1[3] = {0.0f, 0.0f, 0.0f}, g_b3 = 0.0f;
+    const uint64_t n_tiles = (a.n_rec + 63) / 64;
+    for (uint64_t tile = blockIdx.x; tile < n_tiles; tile += gridDim.x) {
+        const float *th = th0 + opaque_zero();
+        const uint64_t e = tile * 64 + lane;
+        const bool valid = e < a.n_rec;
+        TrainRec R{};
+        float g = 0.0f;
+        if (valid) {
+            R = a.rec[e];
+            const uint32_t path = R.pn >> 3;
+            const double n = static_cast<double>(R.pn & 7u);
+            const double r = static_cast<double>(a.r_buf[e]);
+            g = static_cast<float>(a.c[path] * (r * n * dNd - static_cast<double>(R.H)) *
+                                   static_cast<double>(a.mc.out_scale));
+        } else {
+            R.phi = a.mc.in_mean[0];
+        }
+        // forward
+        float x[3], h1[64];
+        net_inputs(a.mc, R.phi, R.k, a.dN, x);
+        net_layer1(th, x, h1);
+#pragma unroll
+        for (int u = 0; u < 64; ++u) HA[lane * TS + u] = h1[u];
+#pragma unroll 1
+        for (int u = 0; u < 64; ++u) HB[lane * TS + u] = net_unit2(th, u, h1);
+        XS[lane * 4 + 0] = x[0];
+        XS[lane * 4 + 1] = x[1];
+        XS[lane * 4 + 2] = x[2];
+        XS[lane * 4 + 3] = 1.0f;
+        GS[lane] = g;
+        // delta2 = g w3 (1 - h2^2)
+#pragma unroll 4
+        for (int u = 0; u < 64; ++u) {
+            const float h = HB[lane * TS + u];
+            HC[lane * TS + u] = (g * th[NET_W3 + u]) * __builtin_fmaf(-h, h, 1.0f);
+        }
+        __syncthreads();
+        // lane = unit: w3, b2, b3
+        {
+            float sw3 = 0.0f, sb2 = 0.0f, sb3 = 0.0f;
+#pragma unroll 4
+            for (int s = 0; s < 64; ++s) {
+                const float gs = GS[s];
+                sw3 = __builtin_fmaf(gs, HB[s * TS + lane], sw3);
+                sb2 += HC[s * TS + lane];
+                sb3 += gs;
+            }
+            g_w3 += sw3;
+            g_b2 += sb2;
+            g_b3 += sb3;
+        }
+        __syncthreads();
+        // delta1 = (W2^T delta2) (1 - h1^2), rows of W2 against this lane's delta2, into HB
+        {
+            float t1[64];
+#pragma unroll
+            for (int v = 0; v < 64; ++v) t1[v] = 0.0f;
+#pragma unroll 1
+            for (int u = 0; u < 64; ++u) {
+                const float d = HC[lane * TS + u];
+#pragma unroll
+                for (int v = 0; v < 64; ++v) t1[v] = __builtin_fmaf(th[NET_W2 + 64 * u + v], d, t1[v]);
+            }
+#pragma unroll
+            for (int v = 0; v < 64; ++v) {
+                const float h = HA[lane * TS + v];
+                HB[lane * TS + v] = t1[v] * __builtin_fmaf(-h, h, 1.0f);
+            }
+        }
+        __syncthreads();
+        // lane = unit: W1, b1
+        {
+            float sb1 = 0.0f, s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
+#pragma unroll 4
+            for (int s = 0; s < 64; ++s) {
+                const float d = HB[s * TS + lane];
+                sb1 += d;
+                s0 = __builtin_fmaf(d, XS[s * 4 + 0], s0);
+                s1 = __builtin_fmaf(d, XS[s * 4 + 1], s1);
+                s2 = __builtin_fmaf(d, XS[s * 4 + 2], s2);
+            }
+            g_b1 += sb1;
+            g_w1[0] += s0;
+            g_w1[1] += s1;
+            g_w1[2] += s2;
+        }
+        // dW2[u][v] += sum_s delta2[s][u] h1[s][v]: M = u, N = v, K = the tile's samples
+        const int row = lane & 31, kh = lane >> 5;
+#pragma unroll 4
+        for (int ks = 0; ks < 32; ++ks) {
+            const int s = 2 * ks + kh;
+            const float a0 = HC[s * TS + row], a1 = HC[s * TS + 32 + row];
+            const float b0 = HA[s * TS + row], b1 = HA[s * TS + 32 + row];
+            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+        }
+        __syncthreads();
+    }
+    // partial gradient of this workgroup
+    float *P = a.part + static_cast<size_t>(blockIdx.x) * NET_N_PARAMS;
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                const int u = 32 * mb + (q & 3) + 8 * (q >> 2) + 4 * (lane >> 5);
+                const int v = 32 * nb + (lane & 31);
+                P[NET_W2 + 64 * u + v] = acc[mb][nb][q];
+            }
+    P[NET_W1 + 3 * lane + 0] = g_w1[0];
+    P[NET_W1 + 3 * lane + 1] = g_w1[1];
+    P[NET_W1 + 3 * lane + 2] = g_w1[2];
+    P[NET_B1 + lane] = g_b1;
+    P[NET_B2 + lane] = g_b2;
+    P[NET_W3 + lane] = g_w3;
+    if (lane == 0) P[NET_B3] = g_b3;
+}
+
+__global__ __launch_bounds__(256) void fpt_train_reduce_kernel(const float *part, int n_part, double *grad) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= NET_N_PARAMS) return;
+    double s = 0.0;
+    for (int w = 0; w < n_part; ++w) s += static_cast<double>(part[static_cast<size_t>(w) * NET_N_PARAMS + j]);
+    grad[j] = s;
+}
+
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+    uint32_t b = __float_as_uint(x);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return static_cast<uint16_t>(b >> 16);
+}
+
+__global__ __launch_bounds__(256) void fpt_adam_kernel(AdamArgs a) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= NET_N_PARAMS) return;
+    const float g = static_cast<float>(a.grad[j]);
+    const float m = a.beta1 * a.m[j] + (1.0f - a.beta1) * g;
+    const float v = a.beta2 * a.v[j] + (1.0f - a.beta2) * g * g;
+    a.m[j] = m;
+    a.v[j] = v;
+    const float mh = m / a.bc1;
+    const float vh = v / a.bc2;
+    const float th = a.theta[j] - a.lr * mh / (sqrtf(vh) + a.eps);
+    a.theta[j] = th;
+    a.bf16[j] = bf16_bits(th);
+}
+
+__global__ __launch_bounds__(256) void fpt_to_bf16_kernel(const float *theta, uint16_t *bf) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < NET_N_PARAMS) bf[j] = bf16_bits(theta[j]);
+}
+
+// ---------------------------------------------------------------------------
+// launches
+// ---------------------------------------------------------------------------
+template <int POT, int BIAS>
+static hipError_t launch_record_t(const RecordArgs &a, hipStream_t s) {
+    const unsigned blocks = (a.n_paths + 255) / 256;
+    hipLaunchKernelGGL((fpt_record_kernel<POT, BIAS>), dim3(blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int POT>
+static hipError_t launch_record_b(int bias, const RecordArgs &a, hipStream_t s) {
+    switch (bias) {
+    case BIAS_NONE: return launch_record_t<POT, BIAS_NONE>(a, s);
+    case BIAS_NOISE_SCALED: return launch_record_t<POT, BIAS_NOISE_SCALED>(a, s);
+    case BIAS_POWER: return launch_record_t<POT, BIAS_POWER>(a, s);
+    case BIAS_MLP: return launch_record_t<POT, BIAS_MLP>(a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_records(int pot, int bias, const RecordArgs &a, hipStream_t s) {
+    if (a.n_paths == 0) return hipSuccess;
+    switch (pot) {
+    case POT_QUADRATIC: return launch_record_b<POT_QUADRATIC>(bias, a, s);
+    case POT_QUADRATIC_BUMP: return launch_record_b<POT_QUADRATIC_BUMP>(bias, a, s);
+    case POT_FLAT: return launch_record_b<POT_FLAT>(bias, a, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_train_loss(const TrainArgs &a, hipStream_t s) {
+    if (a.n_paths <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fpt_train_fwd_kernel, dim3(a.n_paths), dim3(256), 0, s, a, a.theta);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fpt_train_softmax_kernel, dim3(1), dim3(1024), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_train_grad(const TrainArgs &a, hipStream_t s) {
+    if (a.n_part <= 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(fpt_train_bwd_kernel, dim3(a.n_part), dim3(64), 0, s, a, a.theta);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(fpt_train_reduce_kernel, dim3((NET_N_PARAMS + 255) / 256), dim3(256), 0, s, a.part, a.n_part,
+                       a.grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(const AdamArgs &a, hipStream_t s) {
+    hipLaunchKernelGGL(fpt_adam_kernel, dim3((NET_N_PARAMS + 255) / 256), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float *theta, uint16_t *bf, hipStream_t s) {
+    hipLaunchKernelGGL(fpt_to_bf16_kernel, dim3((NET_N_PARAMS + 255) / 256), dim3(256), 0, s, theta, bf);
+    return hipGetLastError();
+}
+
+}  // namespace fpt

@@ -23,6 +23,7 @@
 
 #include "../../include/pyfpt.h"
 #include "fpt_kernels.h"
+#include "fpt_train.h"
 
 using namespace fpt;
 
@@ -657,6 +658,85 @@ int run_batch_impl(const pyfpt_instance *ins, int n_inst, uint64_t seed, pyfpt_r
     return copy_out(P, ws, n_wg, out, stream);
 }
 
+// ----------------------------------------------------------------------------
+// training of the learned proposal
+// ----------------------------------------------------------------------------
+struct DevBuf {
+    void *p = nullptr;
+    ~DevBuf() {
+        if (p) (void)hipFree(p);
+    }
+    int alloc(size_t bytes) {
+        if (p) {
+            (void)hipFree(p);
+            p = nullptr;
+        }
+        if (bytes == 0) bytes = 16;
+        hipError_t e = hipMalloc(&p, bytes);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return fail(PYFPT_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+        }
+        return PYFPT_OK;
+    }
+    template <class T>
+    T *as() const { return static_cast<T *>(p); }
+};
+
+int check_offsets(const uint64_t *off, int64_t n, uint64_t n_rec) {
+    if (off[0] != 0) return fail(PYFPT_EINVAL, "rec_off[0] must be 0");
+    for (int64_t i = 0; i < n; ++i)
+        if (off[i + 1] < off[i]) return fail(PYFPT_EINVAL, "rec_off not ascending at %lld", static_cast<long long>(i));
+    if (n_rec != UINT64_MAX && off[n] != n_rec) return fail(PYFPT_EINVAL, "rec_off[n_paths] must equal n_rec");
+    return PYFPT_OK;
+}
+
+MlpConsts mlp_consts(const pyfpt_mlp &m, double target_N) {
+    MlpConsts c{};
+    for (int q = 0; q < 3; ++q) {
+        c.in_mean[q] = m.in_mean[q];
+        c.in_inv[q] = m.in_inv_scale[q];
+    }
+    c.out_scale = m.out_scale;
+    c.target_N = static_cast<float>(target_N);
+    return c;
+}
+
+// Replay on the device: buffers already on the device; outputs per path on the device.
+int records_device(const Prepared &P, uint64_t seed, int group, const uint64_t *d_t, uint32_t n_paths,
+                   const uint64_t *d_off, TrainRec *d_rec, uint32_t *d_k, double *d_lw, int32_t *d_st,
+                   uint64_t *d_nrec, hipStream_t stream) {
+    RecordArgs ra{};
+    ra.inst = P.inst[0];
+    ra.t_ids = d_t;
+    ra.n_paths = n_paths;
+    ra.key0 = static_cast<uint32_t>(seed);
+    ra.key1 = static_cast<uint32_t>(seed >> 32);
+    ra.group = group;
+    ra.mlp_every = P.mlp_every;
+    ra.mlp_params = P.mlp_params;
+    ra.rec_off = d_off;
+    ra.rec = d_rec;
+    ra.k_out = d_k;
+    ra.lw_out = d_lw;
+    ra.st_out = d_st;
+    ra.n_rec_out = d_nrec;
+    HIP_TRY(launch_records(P.pot, P.bias, ra, stream), "launch record kernel");
+    return PYFPT_OK;
+}
+
+int backward_groups(uint64_t n_rec) {
+    int cus = 0;
+    {
+        Device *d = nullptr;
+        std::lock_guard<std::mutex> lock(g_mu);
+        if (get_device(&d) == PYFPT_OK) cus = d->cus;
+    }
+    const uint64_t tiles = (n_rec + 63) / 64;
+    const uint64_t cap = static_cast<uint64_t>(cus > 0 ? cus : 1) * 3;
+    return static_cast<int>(std::max<uint64_t>(1, std::min(tiles, cap)));
+}
+
 }  // namespace
 
 extern "C" {
@@ -762,6 +842,285 @@ int pyfpt_mlp_forward(const pyfpt_mlp *mlp, double target_N, const float *phi, c
     c.target_N = static_cast<float>(target_N);
     HIP_TRY(launch_mlp_forward(static_cast<const uint16_t *>(mlp->params), c, phi, N, r, n,
                                static_cast<hipStream_t>(stream)), "launch mlp forward");
+    return PYFPT_OK;
+}
+
+int pyfpt_proposal_records(const pyfpt_instance *inst, uint64_t seed, const uint64_t *t_ids, int32_t n_paths,
+                           int32_t group, const uint64_t *rec_off, pyfpt_record *rec, uint32_t *k_out,
+                           double *lw_out, int32_t *status_out, const pyfpt_options *opt) {
+    if (!inst || n_paths < 0 || (n_paths > 0 && (!t_ids || !rec_off || !k_out || !lw_out || !status_out)))
+        return fail(PYFPT_EINVAL, "NULL argument or n_paths < 0");
+    if (group != 1 && group != 4) return fail(PYFPT_EINVAL, "group must be 1 or 4");
+    if (n_paths >= (1 << 29)) return fail(PYFPT_EINVAL, "n_paths must be < 2^29");
+    Prepared P;
+    int rc = prepare(inst, 1, P);
+    if (rc) return rc;
+    if (n_paths == 0) return PYFPT_OK;
+    if ((rc = check_offsets(rec_off, n_paths, UINT64_MAX))) return rc;
+    const uint64_t n_rec = rec_off[n_paths];
+    if (n_rec > 0 && !rec) return fail(PYFPT_EINVAL, "NULL record array");
+    hipStream_t stream = opt ? static_cast<hipStream_t>(opt->stream) : nullptr;
+    DevBuf t, off, r, k, lw, st, nr;
+    if ((rc = t.alloc(8ull * n_paths)) || (rc = off.alloc(8ull * (n_paths + 1))) || (rc = r.alloc(16ull * n_rec)) ||
+        (rc = k.alloc(4ull * n_paths)) || (rc = lw.alloc(8ull * n_paths)) || (rc = st.alloc(4ull * n_paths)) ||
+        (rc = nr.alloc(8ull * n_paths)))
+        return rc;
+    HIP_TRY(hipMemcpyAsync(t.p, t_ids, 8ull * n_paths, hipMemcpyHostToDevice, stream), "upload ids");
+    HIP_TRY(hipMemcpyAsync(off.p, rec_off, 8ull * (n_paths + 1), hipMemcpyHostToDevice, stream), "upload offsets");
+    if ((rc = records_device(P, seed, group, t.as<uint64_t>(), static_cast<uint32_t>(n_paths), off.as<uint64_t>(),
+                             r.as<TrainRec>(), k.as<uint32_t>(), lw.as<double>(), st.as<int32_t>(), nr.as<uint64_t>(),
+                             stream)))
+        return rc;
+    if (n_rec) HIP_TRY(hipMemcpyAsync(rec, r.p, 16ull * n_rec, hipMemcpyDeviceToHost, stream), "download records");
+    HIP_TRY(hipMemcpyAsync(k_out, k.p, 4ull * n_paths, hipMemcpyDeviceToHost, stream), "download k");
+    HIP_TRY(hipMemcpyAsync(lw_out, lw.p, 8ull * n_paths, hipMemcpyDeviceToHost, stream), "download lw");
+    HIP_TRY(hipMemcpyAsync(status_out, st.p, 4ull * n_paths, hipMemcpyDeviceToHost, stream), "download status");
+    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    return PYFPT_OK;
+}
+
+int pyfpt_proposal_loss_grad(const pyfpt_mlp *net, double target_N, double dN, const float *theta,
+                             const pyfpt_record *rec, uint64_t n_rec, const uint64_t *rec_off, int32_t n_paths,
+                             const double *lw0, double n_total, double *loss, double *grad, double *lw_theta,
+                             const pyfpt_options *opt) {
+    if (!net || !theta || !rec_off || !lw0 || !loss || !grad || !lw_theta || (n_rec > 0 && !rec))
+        return fail(PYFPT_EINVAL, "NULL argument");
+    if (n_paths < 1 || n_paths >= (1 << 29)) return fail(PYFPT_EINVAL, "n_paths must be 1 .. 2^29-1");
+    if (!(dN > 0) || !std::isfinite(dN) || !(n_total > 0) || !std::isfinite(target_N))
+        return fail(PYFPT_EINVAL, "need finite dN > 0, n_total > 0 and finite target_N");
+    int rc = check_offsets(rec_off, n_paths, n_rec);
+    if (rc) return rc;
+    for (uint64_t e = 0; e < n_rec; ++e) {
+        const uint32_t pn = rec[e].path_n;
+        if ((pn >> 3) >= static_cast<uint32_t>(n_paths) || (pn & 7u) < 1 || (pn & 7u) > 4)
+            return fail(PYFPT_EINVAL, "record %llu: path index or step count out of range",
+                        static_cast<unsigned long long>(e));
+    }
+    hipStream_t stream = opt ? static_cast<hipStream_t>(opt->stream) : nullptr;
+    const int n_part = backward_groups(n_rec);
+    DevBuf r, off, th, rb, lwt, l0, c, ls, part, g;
+    if ((rc = r.alloc(16ull * n_rec)) || (rc = off.alloc(8ull * (n_paths + 1))) || (rc = th.alloc(4ull * NET_N_PARAMS)) ||
+        (rc = rb.alloc(4ull * n_rec)) || (rc = lwt.alloc(8ull * n_paths)) || (rc = l0.alloc(8ull * n_paths)) ||
+        (rc = c.alloc(8ull * n_paths)) || (rc = ls.alloc(8)) ||
+        (rc = part.alloc(4ull * NET_N_PARAMS * static_cast<uint64_t>(n_part))) || (rc = g.alloc(8ull * NET_N_PARAMS)))
+        return rc;
+    if (n_rec) HIP_TRY(hipMemcpyAsync(r.p, rec, 16ull * n_rec, hipMemcpyHostToDevice, stream), "upload records");
+    HIP_TRY(hipMemcpyAsync(off.p, rec_off, 8ull * (n_paths + 1), hipMemcpyHostToDevice, stream), "upload offsets");
+    HIP_TRY(hipMemcpyAsync(th.p, theta, 4ull * NET_N_PARAMS, hipMemcpyHostToDevice, stream), "upload theta");
+    HIP_TRY(hipMemcpyAsync(l0.p, lw0, 8ull * n_paths, hipMemcpyHostToDevice, stream), "upload lw0");
+    TrainArgs ta{};
+    ta.rec = r.as<TrainRec>();
+    ta.n_rec = n_rec;
+    ta.rec_off = off.as<uint64_t>();
+    ta.n_paths = n_paths;
+    ta.n_part = n_part;
+    ta.theta = th.as<float>();
+    ta.mc = mlp_consts(*net, target_N);
+    ta.dN = static_cast<float>(dN);
+    ta.r_buf = rb.as<float>();
+    ta.lw_theta = lwt.as<double>();
+    ta.lw0 = l0.as<double>();
+    ta.n_total = n_total;
+    ta.c = c.as<double>();
+    ta.loss = ls.as<double>();
+    ta.part = part.as<float>();
+    ta.grad = g.as<double>();
+    HIP_TRY(launch_train_loss(ta, stream), "launch loss kernels");
+    HIP_TRY(launch_train_grad(ta, stream), "launch gradient kernels");
+    HIP_TRY(hipMemcpyAsync(loss, ls.p, 8, hipMemcpyDeviceToHost, stream), "download loss");
+    HIP_TRY(hipMemcpyAsync(grad, g.p, 8ull * NET_N_PARAMS, hipMemcpyDeviceToHost, stream), "download grad");
+    HIP_TRY(hipMemcpyAsync(lw_theta, lwt.p, 8ull * n_paths, hipMemcpyDeviceToHost, stream), "download lw_theta");
+    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+    return PYFPT_OK;
+}
+
+int pyfpt_train_proposal(const pyfpt_instance *inst, uint64_t seed, const pyfpt_train_config *cfg, float *theta,
+                         uint16_t *params_bf16, pyfpt_train_report *report, const pyfpt_options *opt) {
+    if (!inst || !cfg || !theta || !params_bf16 || !report) return fail(PYFPT_EINVAL, "NULL argument");
+    if (inst->bias.kind != PYFPT_BIAS_MLP) return fail(PYFPT_EINVAL, "the instance's bias must be the learned bias");
+    if (cfg->group != 1 && cfg->group != 4) return fail(PYFPT_EINVAL, "group must be 1 or 4");
+    if (cfg->rounds < 1 || cfg->steps < 1 || cfg->n_sample < 1 || cfg->max_paths < 0)
+        return fail(PYFPT_EINVAL, "need rounds >= 1, steps >= 1, n_sample >= 1, max_paths >= 0");
+    if (!(cfg->window_hi > cfg->window_lo) || !std::isfinite(cfg->window_lo) || !std::isfinite(cfg->window_hi))
+        return fail(PYFPT_EINVAL, "need a finite window lo < hi");
+    if (!(cfg->lr > 0) || !(cfg->beta1 >= 0 && cfg->beta1 < 1) || !(cfg->beta2 >= 0 && cfg->beta2 < 1) || !(cfg->eps > 0))
+        return fail(PYFPT_EINVAL, "bad Adam constants");
+    if (cfg->n_sample >= (1ull << 32)) return fail(PYFPT_EINVAL, "n_sample must be < 2^32");
+    for (int j = 0; j < NET_N_PARAMS; ++j)
+        if (!std::isfinite(theta[j])) return fail(PYFPT_EINVAL, "theta[%d] is not finite", j);
+    hipStream_t stream = opt ? static_cast<hipStream_t>(opt->stream) : nullptr;
+    int rc;
+    // device copies of the network: master, Adam moments, bfloat16 copy for sampling
+    DevBuf th, am, av, bf, g;
+    if ((rc = th.alloc(4ull * NET_N_PARAMS)) || (rc = am.alloc(4ull * NET_N_PARAMS)) || (rc = av.alloc(4ull * NET_N_PARAMS)) ||
+        (rc = bf.alloc(2ull * NET_N_PARAMS)) || (rc = g.alloc(8ull * NET_N_PARAMS)))
+        return rc;
+    HIP_TRY(hipMemcpyAsync(th.p, theta, 4ull * NET_N_PARAMS, hipMemcpyHostToDevice, stream), "upload theta");
+    HIP_TRY(hipMemsetAsync(am.p, 0, 4ull * NET_N_PARAMS, stream), "clear Adam m");
+    HIP_TRY(hipMemsetAsync(av.p, 0, 4ull * NET_N_PARAMS, stream), "clear Adam v");
+    HIP_TRY(launch_to_bf16(th.as<float>(), bf.as<uint16_t>(), stream), "launch bf16 copy");
+    // sampling instance: the current network, n_sample runs
+    pyfpt_instance I = *inst;
+    I.bias.mlp.params = bf.p;
+    I.n_traj = cfg->n_sample;
+    const uint64_t ns = cfg->n_sample;
+    DevBuf dk, dlw, dphi, dst;
+    if ((rc = dk.alloc(4 * ns)) || (rc = dlw.alloc(8 * ns)) || (rc = dphi.alloc(4 * ns)) || (rc = dst.alloc(4 * ns)))
+        return rc;
+    pyfpt_layout lay{};
+    if ((rc = pyfpt_result_layout(I.bins.n_bins, I.bins.n_sub ? I.bins.n_sub : kDefaultNsub, &lay))) return rc;
+    std::vector<uint64_t> counts(lay.n_counts);
+    std::vector<double> values(lay.n_values);
+    std::vector<uint32_t> hk(ns);
+    std::vector<double> hlw(ns);
+    std::vector<int32_t> hst(ns);
+    hipEvent_t ev[4];
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+    struct EvFree {
+        hipEvent_t *e;
+        ~EvFree() {
+            for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]);
+        }
+    } evfree{ev};
+    int64_t t_adam = 0;
+    for (int round = 0; round < cfg->rounds; ++round) {
+        pyfpt_train_report &R = report[round];
+        std::memset(&R, 0, sizeof R);
+        const uint64_t seed_r = seed + static_cast<uint64_t>(round);
+        // 1. sample from the current proposal, every run dumped
+        pyfpt_options so{};
+        so.stream = stream;
+        so.block = opt && opt->block ? opt->block : 256;
+        so.wg_per_cu = opt && opt->wg_per_cu ? opt->wg_per_cu : 1;
+        so.chunk = opt && opt->chunk ? opt->chunk : 1;
+        so.dump.n = ns;
+        so.dump.stride = 1;
+        so.dump.k = dk.as<uint32_t>();
+        so.dump.lw = dlw.as<double>();
+        so.dump.phi = dphi.as<float>();
+        so.dump.status = dst.as<int32_t>();
+        pyfpt_result res{counts.data(), values.data(), 0};
+        HIP_TRY(hipEventRecord(ev[0], stream), "event");
+        if ((rc = run_batch_impl(&I, 1, seed_r, &res, &so))) return rc;
+        HIP_TRY(hipEventRecord(ev[1], stream), "event");
+        HIP_TRY(hipMemcpyAsync(hk.data(), dk.p, 4 * ns, hipMemcpyDeviceToHost, stream), "download k");
+        HIP_TRY(hipMemcpyAsync(hlw.data(), dlw.p, 8 * ns, hipMemcpyDeviceToHost, stream), "download lw");
+        HIP_TRY(hipMemcpyAsync(hst.data(), dst.p, 4 * ns, hipMemcpyDeviceToHost, stream), "download status");
+        HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        HIP_TRY(hipEventElapsedTime(&R.ms_sample, ev[0], ev[1]), "hipEventElapsedTime");
+        // 2. the runs that ended in the window (right-closed, as the bins)
+        std::vector<uint64_t> ids;
+        std::vector<double> lw0;
+        double mx = -INFINITY;
+        for (uint64_t t = 0; t < ns; ++t) {
+            if (hst[t] != PYFPT_ST_ENDED) continue;
+            const double N = static_cast<double>(hk[t]) * I.dN;
+            if (N > cfg->window_lo && N <= cfg->window_hi) {
+                R.n_window += 1;
+                if (cfg->max_paths == 0 || static_cast<int32_t>(ids.size()) < cfg->max_paths) {
+                    ids.push_back(t);
+                    lw0.push_back(hlw[t]);
+                    mx = std::max(mx, hlw[t]);
+                }
+            }
+        }
+        R.n_used = static_cast<int32_t>(ids.size());
+        if (ids.empty()) {
+            R.loss_first = R.loss_last = -INFINITY;
+            continue;
+        }
+        {
+            double s1 = 0, s2 = 0;
+            for (double x : lw0) {
+                s1 += std::exp(x - mx);
+                s2 += std::exp(2 * (x - mx));
+            }
+            R.kish_window = s1 * s1 / s2;
+        }
+        const uint32_t np = static_cast<uint32_t>(ids.size());
+        std::vector<uint64_t> off(np + 1, 0);
+        for (uint32_t i = 0; i < np; ++i) off[i + 1] = off[i] + (hk[ids[i]] + cfg->group - 1) / cfg->group;
+        const uint64_t n_rec = off[np];
+        R.n_records = n_rec;
+        // 3. replay into records under the proposal that drew the runs
+        Prepared P;
+        if ((rc = prepare(&I, 1, P))) return rc;
+        DevBuf dt, doff, drec, rk, rlw, rst, rnr, rb, lwt, l0, c, ls, part;
+        const int n_part = backward_groups(n_rec);
+        if ((rc = dt.alloc(8ull * np)) || (rc = doff.alloc(8ull * (np + 1))) || (rc = drec.alloc(16ull * n_rec)) ||
+            (rc = rk.alloc(4ull * np)) || (rc = rlw.alloc(8ull * np)) || (rc = rst.alloc(4ull * np)) ||
+            (rc = rnr.alloc(8ull * np)) || (rc = rb.alloc(4ull * n_rec)) || (rc = lwt.alloc(8ull * np)) ||
+            (rc = l0.alloc(8ull * np)) || (rc = c.alloc(8ull * np)) || (rc = ls.alloc(8)) ||
+            (rc = part.alloc(4ull * NET_N_PARAMS * static_cast<uint64_t>(n_part))))
+            return rc;
+        HIP_TRY(hipMemcpyAsync(dt.p, ids.data(), 8ull * np, hipMemcpyHostToDevice, stream), "upload ids");
+        HIP_TRY(hipMemcpyAsync(doff.p, off.data(), 8ull * (np + 1), hipMemcpyHostToDevice, stream), "upload offsets");
+        HIP_TRY(hipMemcpyAsync(l0.p, lw0.data(), 8ull * np, hipMemcpyHostToDevice, stream), "upload lw0");
+        HIP_TRY(hipEventRecord(ev[1], stream), "event");
+        if ((rc = records_device(P, seed_r, cfg->group, dt.as<uint64_t>(), np, doff.as<uint64_t>(), drec.as<TrainRec>(),
+                                 rk.as<uint32_t>(), rlw.as<double>(), rst.as<int32_t>(), rnr.as<uint64_t>(), stream)))
+            return rc;
+        HIP_TRY(hipEventRecord(ev[2], stream), "event");
+        {
+            std::vector<uint32_t> k2(np);
+            std::vector<double> lw2(np);
+            HIP_TRY(hipMemcpyAsync(k2.data(), rk.p, 4ull * np, hipMemcpyDeviceToHost, stream), "download k");
+            HIP_TRY(hipMemcpyAsync(lw2.data(), rlw.p, 8ull * np, hipMemcpyDeviceToHost, stream), "download lw");
+            HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+            for (uint32_t i = 0; i < np; ++i)
+                if (k2[i] != hk[ids[i]] || lw2[i] != lw0[i])
+                    return fail(PYFPT_EDEVICE, "replay of run %llu differs from the sampled run",
+                                static_cast<unsigned long long>(ids[i]));
+        }
+        HIP_TRY(hipEventElapsedTime(&R.ms_records, ev[1], ev[2]), "hipEventElapsedTime");
+        // 4. Adam steps on log M2
+        TrainArgs ta{};
+        ta.rec = drec.as<TrainRec>();
+        ta.n_rec = n_rec;
+        ta.rec_off = doff.as<uint64_t>();
+        ta.n_paths = static_cast<int32_t>(np);
+        ta.n_part = n_part;
+        ta.theta = th.as<float>();
+        ta.mc = P.inst[0].mlp;
+        ta.dN = P.inst[0].c.dN;
+        ta.r_buf = rb.as<float>();
+        ta.lw_theta = lwt.as<double>();
+        ta.lw0 = l0.as<double>();
+        ta.n_total = static_cast<double>(ns);
+        ta.c = c.as<double>();
+        ta.loss = ls.as<double>();
+        ta.part = part.as<float>();
+        ta.grad = g.as<double>();
+        HIP_TRY(hipEventRecord(ev[2], stream), "event");
+        for (int step = 0; step < cfg->steps; ++step) {
+            HIP_TRY(launch_train_loss(ta, stream), "launch loss kernels");
+            if (step == 0) HIP_TRY(hipMemcpyAsync(&R.loss_first, ls.p, 8, hipMemcpyDeviceToHost, stream), "download loss");
+            HIP_TRY(launch_train_grad(ta, stream), "launch gradient kernels");
+            t_adam += 1;
+            AdamArgs aa{};
+            aa.theta = th.as<float>();
+            aa.m = am.as<float>();
+            aa.v = av.as<float>();
+            aa.grad = g.as<double>();
+            aa.bf16 = bf.as<uint16_t>();
+            aa.lr = cfg->lr;
+            aa.beta1 = cfg->beta1;
+            aa.beta2 = cfg->beta2;
+            aa.eps = cfg->eps;
+            aa.bc1 = static_cast<float>(1.0 - std::pow(static_cast<double>(cfg->beta1), static_cast<double>(t_adam)));
+            aa.bc2 = static_cast<float>(1.0 - std::pow(static_cast<double>(cfg->beta2), static_cast<double>(t_adam)));
+            HIP_TRY(launch_adam(aa, stream), "launch Adam");
+        }
+        // loss at the updated parameters
+        HIP_TRY(launch_train_loss(ta, stream), "launch loss kernels");
+        HIP_TRY(hipEventRecord(ev[3], stream), "event");
+        HIP_TRY(hipMemcpyAsync(&R.loss_last, ls.p, 8, hipMemcpyDeviceToHost, stream), "download loss");
+        HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        HIP_TRY(hipEventElapsedTime(&R.ms_optimise, ev[2], ev[3]), "hipEventElapsedTime");
+    }
+    HIP_TRY(hipMemcpyAsync(theta, th.p, 4ull * NET_N_PARAMS, hipMemcpyDeviceToHost, stream), "download theta");
+    HIP_TRY(hipMemcpyAsync(params_bf16, bf.p, 2ull * NET_N_PARAMS, hipMemcpyDeviceToHost, stream), "download params");
+    HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
     return PYFPT_OK;
 }
 
