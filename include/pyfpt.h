@@ -270,7 +270,11 @@ int pyfpt_proposal_records(const pyfpt_instance *inst, uint64_t seed, const uint
                            double *lw_out, int32_t *status_out, const pyfpt_options *opt);
 
 /*
- * log M2(theta) and its gradient from records (host arrays): theta holds the 4481 binary32
+ * The objective and its gradient from records (host arrays).  objective 0: log M2(theta) as
+ * above; objective 1: the cross entropy sum_i c_i ln w_theta,i with c_i = w_0,i / sum_j w_0,j,
+ * i.e. the Kullback-Leibler divergence of the proposal from the target restricted to the
+ * window, up to a theta-independent constant (its minimiser is the same zero-variance
+ * proposal, and its path weights do not depend on theta).  theta holds the 4481 binary32
  * master parameters in the order of pyfpt_mlp; net supplies the input normalisation and
  * out_scale (its params are not read); dN as in the sampling run; lw0[i] = ln w_0 of path i;
  * n_total = number of runs drawn.  Outputs: *loss, grad[4481] (binary64), lw_theta[n_paths].
@@ -280,8 +284,8 @@ int pyfpt_proposal_records(const pyfpt_instance *inst, uint64_t seed, const uint
  */
 int pyfpt_proposal_loss_grad(const pyfpt_mlp *net, double target_N, double dN, const float *theta,
                              const pyfpt_record *rec, uint64_t n_rec, const uint64_t *rec_off, int32_t n_paths,
-                             const double *lw0, double n_total, double *loss, double *grad, double *lw_theta,
-                             const pyfpt_options *opt);
+                             const double *lw0, double n_total, int32_t objective, double *loss, double *grad,
+                             double *lw_theta, const pyfpt_options *opt);
 
 typedef struct pyfpt_train_config {
     double window_lo, window_hi;     /* target window B* = (lo, hi] in N */
@@ -291,13 +295,15 @@ typedef struct pyfpt_train_config {
     int32_t steps;                   /* Adam steps per round */
     int32_t group;                   /* 1 or 4: the network's evaluation interval */
     float lr, beta1, beta2, eps;     /* Adam */
+    int32_t objective;               /* 0: log M2; 1: cross entropy (see pyfpt_proposal_loss_grad) */
+    int32_t reserved;
 } pyfpt_train_config;
 
 typedef struct pyfpt_train_report {
     int32_t n_window;                /* runs of the round that ended in the window */
     int32_t n_used;                  /* of which used for training */
     uint64_t n_records;
-    double loss_first, loss_last;    /* log M2 at the round's first and last Adam step */
+    double loss_first, loss_last;    /* objective before the round's first and after its last Adam step */
     double kish_window;              /* sum w_0 over the used window runs squared / sum w_0^2 */
     float ms_sample, ms_records, ms_optimise;
 } pyfpt_train_report;
@@ -306,7 +312,7 @@ typedef struct pyfpt_train_report {
  * Train the learned proposal of `inst` (bias.kind = PYFPT_BIAS_MLP; its normalisation,
  * out_scale, eval_every and target_N are used, its params are not): each round draws
  * cfg->n_sample runs from the current network (seed + round), keeps the runs that ended in the
- * window, replays them into records and takes cfg->steps Adam steps on log M2.  theta (host,
+ * window, replays them into records and takes cfg->steps Adam steps on the objective.  theta (host,
  * 4481 binary32) is the starting master copy on entry and the trained one on return;
  * params_bf16 (host, 4481) receives the bfloat16 copy for pyfpt_run.  report has cfg->rounds
  * entries.  EINVAL for a bad configuration.  The call synchronises.

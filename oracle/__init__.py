@@ -100,7 +100,7 @@ def lib():
                                      u64p, f64p, i32p]
         L.oracle_records.restype = ctypes.c_int64
         L.oracle_loss_grad.argtypes = [ctypes.POINTER(_Params), f64p, vp, u64p, ctypes.c_int64, f64p,
-                                       ctypes.c_double, f64p, f64p, f64p, f64p]
+                                       ctypes.c_double, ctypes.c_int, f64p, f64p, f64p, f64p]
         _lib = L
     return _lib
 
@@ -239,9 +239,10 @@ def records(model: Model, seed: int, t_ids, E: int) -> Records:
     return Records(rec, off, k, lw, st)
 
 
-def loss_grad(model: Model, theta, recs: Records, lw0, n_total: float):
-    """log M2(theta) over the window paths of `recs`, its gradient (4481) and ln w_theta per
-    path.  model supplies the input normalisation, out_scale, N* and dN."""
+def loss_grad(model: Model, theta, recs: Records, lw0, n_total: float, objective: int = 0):
+    """Objective 0: log M2(theta); objective 1: the cross entropy sum_i c_i ln w_theta,i with
+    c_i proportional to w_0,i.  Returns the loss, its gradient (4481) and ln w_theta per path.
+    model supplies the input normalisation, out_scale, N* and dN."""
     L = lib()
     th = np.ascontiguousarray(theta, np.float64)
     assert th.size == 4481
@@ -254,7 +255,7 @@ def loss_grad(model: Model, theta, recs: Records, lw0, n_total: float):
     scratch = np.zeros(max(n, 1) * 4481)
     L.oracle_loss_grad(ctypes.byref(P), _ptr(th, ctypes.c_double), ctypes.c_void_p(recs.rec.ctypes.data),
                        _ptr(recs.off, ctypes.c_uint64), n, _ptr(lw0, ctypes.c_double), float(n_total),
-                       _ptr(loss, ctypes.c_double), _ptr(grad, ctypes.c_double), _ptr(lwt, ctypes.c_double),
+                       int(objective), _ptr(loss, ctypes.c_double), _ptr(grad, ctypes.c_double), _ptr(lwt, ctypes.c_double),
                        _ptr(scratch, ctypes.c_double))
     return float(loss[0]), grad, lwt
 

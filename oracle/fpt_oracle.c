@@ -738,15 +738,18 @@ static double net_f64(const oracle_params *P, const double *th, float phi, uint3
     return (double)P->out_scale * o;
 }
 
-/* Loss log M2(theta) = log( sum_{i in B*} w_0,i w_theta,i / n_total ) over the window paths
- * given by their records and sampled weights lw0, and its gradient with respect to the 4481
- * parameters:
- *   d log M2 / d theta = sum_i c_i sum_e (r_e n_e dN - H_e) d r_e / d theta,
- *   c_i = w_0,i w_theta,i / sum_j w_0,j w_theta,j.
+/* Two objectives over the window paths given by their records and sampled weights lw0:
+ *   objective 0, the second moment:  L = log M2(theta) = log( sum_i w_0,i w_theta,i / n_total ),
+ *       dL/dtheta = sum_i c_i d ln w_theta,i / dtheta,  c_i = w_0,i w_theta,i / sum_j w_0,j w_theta,j;
+ *   objective 1, the cross entropy of the proposal against the target restricted to the
+ *       window, KL(p_T 1_B / P(B) || q_theta) up to a constant:  L = sum_i c_i ln w_theta,i,
+ *       c_i = w_0,i / sum_j w_0,j (the weights do not depend on theta),
+ *       dL/dtheta = sum_i c_i d ln w_theta,i / dtheta.
+ * In both, d ln w_theta / dtheta = sum_e (r_e n_e dN - H_e) d r_e / dtheta.
  * grad_path (n_paths x 4481 scratch) keeps the per-path sums so the total is summed in path
  * order. */
 void oracle_loss_grad(const oracle_params *P, const double *theta, const oracle_record *rec, const uint64_t *rec_off,
-                      int64_t n_paths, const double *lw0, double n_total, double *loss, double *grad,
+                      int64_t n_paths, const double *lw0, double n_total, int objective, double *loss, double *grad,
                       double *lw_theta, double *grad_path)
 {
     const float dN_f = (float)P->dN;
@@ -763,11 +766,18 @@ void oracle_loss_grad(const oracle_params *P, const double *theta, const oracle_
         }
         lw_theta[i] = s;
     }
+    const double use_t = objective == 0 ? 1.0 : 0.0;
     double M = -INFINITY;
-    for (int64_t i = 0; i < n_paths; ++i) M = fmax(M, lw0[i] + lw_theta[i]);
+    for (int64_t i = 0; i < n_paths; ++i) M = fmax(M, lw0[i] + use_t * lw_theta[i]);
     double S = 0.0;
-    for (int64_t i = 0; i < n_paths; ++i) S += exp(lw0[i] + lw_theta[i] - M);
-    *loss = M + log(S) - log(n_total);
+    for (int64_t i = 0; i < n_paths; ++i) S += exp(lw0[i] + use_t * lw_theta[i] - M);
+    if (objective == 0) {
+        *loss = M + log(S) - log(n_total);
+    } else {
+        double L = 0.0;
+        for (int64_t i = 0; i < n_paths; ++i) L += exp(lw0[i] - M) / S * lw_theta[i];
+        *loss = L;
+    }
     const double *W2 = theta + 256, *w3 = theta + 4416;
     const double osc = (double)P->out_scale;
 #ifdef _OPENMP
@@ -776,7 +786,7 @@ void oracle_loss_grad(const oracle_params *P, const double *theta, const oracle_
     for (int64_t i = 0; i < n_paths; ++i) {
         double *g = grad_path + (size_t)i * 4481;
         for (int j = 0; j < 4481; ++j) g[j] = 0.0;
-        const double ci = exp(lw0[i] + lw_theta[i] - M) / S;
+        const double ci = exp(lw0[i] + use_t * lw_theta[i] - M) / S;
         double x[3], h1[64], h2[64], d2[64];
         for (uint64_t e = rec_off[i]; e < rec_off[i + 1]; ++e) {
             const double r = net_f64(P, theta, rec[e].phi, rec[e].k, dN_f, x, h1, h2);

@@ -340,8 +340,10 @@ def proposal_records(inst, seed: int, t_ids, k, group: int) -> Records:
     return Records(rec, off, k_out.astype(np.uint64), lw_out, st_out)
 
 
-def proposal_loss_grad(params, target_N: float, dN: float, theta, recs: Records, lw0, n_total: float):
-    """log M2(theta), its gradient (4481, binary64) and ln w_theta per path, from records."""
+def proposal_loss_grad(params, target_N: float, dN: float, theta, recs: Records, lw0, n_total: float,
+                       objective: int = 0):
+    """The objective (0: log M2, 1: cross entropy), its gradient (4481, binary64) and ln w_theta
+    per path, from records."""
     _torch()
     keep: list = []
     m = mlp_struct(params, keep)
@@ -357,13 +359,14 @@ def proposal_loss_grad(params, target_N: float, dN: float, theta, recs: Records,
     opt = L.pyfpt_options()
     opt.stream = ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
     L.check(L.load().pyfpt_proposal_loss_grad(ctypes.byref(m), float(target_N), float(dN), _ptr(th), _ptr(rec),
-                                              rec.size, _ptr(off), n, _ptr(lw0), float(n_total), _ptr(loss),
+                                              rec.size, _ptr(off), n, _ptr(lw0), float(n_total), int(objective),
+                                              _ptr(loss),
                                               _ptr(grad), _ptr(lwt), ctypes.byref(opt)))
     return float(loss[0]), grad, lwt
 
 
 def train_proposal(inst, seed: int, theta, *, window, n_sample: int, rounds: int, steps: int, max_paths: int = 0,
-                   lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8):
+                   lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, objective: int = 0):
     """Train the learned proposal of `inst` (pyfpt_train_proposal).  Returns (theta, bf16 bits,
     list of per-round report dicts)."""
     _torch()
@@ -372,7 +375,8 @@ def train_proposal(inst, seed: int, theta, *, window, n_sample: int, rounds: int
     th = np.ascontiguousarray(theta, np.float32).copy()
     bf = np.zeros(4481, np.uint16)
     cfg = L.pyfpt_train_config(float(window[0]), float(window[1]), int(n_sample), int(max_paths), int(rounds),
-                               int(steps), int(inst.mlp.eval_every), float(lr), float(beta1), float(beta2), float(eps))
+                               int(steps), int(inst.mlp.eval_every), float(lr), float(beta1), float(beta2), float(eps),
+                               int(objective), 0)
     rep = (L.pyfpt_train_report * rounds)()
     opt = L.pyfpt_options()
     opt.stream = ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)

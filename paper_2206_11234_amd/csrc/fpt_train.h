@@ -43,6 +43,8 @@ struct TrainArgs {
     const uint64_t *rec_off;    // n_paths + 1
     int32_t n_paths;
     int32_t n_part;             // workgroups of the backward pass
+    int32_t objective;          // 0: log M2 (c ~ w_0 w_theta); 1: cross entropy (c ~ w_0)
+    int32_t pad0;
     const float *theta;         // binary32 master parameters
     MlpConsts mc;               // input normalisation, output scale, N*
     float dN;                   // binary32 dN

@@ -13,7 +13,10 @@
 //                        so the replay reproduces the sampled runs) and writes their records;
 //   fpt_train_fwd_kernel r_theta per record (binary32 network on the master weights), per-path
 //                        sum of ln w_theta in binary64 (one workgroup per path, fixed order);
-//   fpt_train_softmax_kernel  c_i = w_0,i w_theta,i / sum_j w_0,j w_theta,j and log M2;
+//   fpt_train_softmax_kernel  c_i = w_0,i w_theta,i / sum_j w_0,j w_theta,j and log M2, or for
+//                        the cross-entropy objective c_i = w_0,i / sum_j w_0,j and
+//                        sum_i c_i ln w_theta,i (the KL divergence of the proposal from the
+//                        target restricted to the window, up to a constant);
 //   fpt_train_bwd_kernel gradient of log M2: per record the coefficient
 //                        c_i (r n dN - H) out_scale multiplies d(w3.h2 + b3)/d theta; each lane
 //                        back-propagates one record, and the weight gradient of the 64x64 layer,
@@ -174,8 +177,9 @@ __global__ __launch_bounds__(256) void fpt_train_fwd_kernel(TrainArgs a, const f
 __global__ __launch_bounds__(1024) void fpt_train_softmax_kernel(TrainArgs a) {
     __shared__ double red[1024];
     const int tid = threadIdx.x;
+    const double use_t = a.objective == 0 ? 1.0 : 0.0;
     double m = -INFINITY;
-    for (int i = tid; i < a.n_paths; i += 1024) m = fmax(m, a.lw0[i] + a.lw_theta[i]);
+    for (int i = tid; i < a.n_paths; i += 1024) m = fmax(m, a.lw0[i] + use_t * a.lw_theta[i]);
     red[tid] = m;
     __syncthreads();
     for (int w = 512; w > 0; w >>= 1) {
@@ -185,7 +189,7 @@ __global__ __launch_bounds__(1024) void fpt_train_softmax_kernel(TrainArgs a) {
     const double M = red[0];
     __syncthreads();
     double s = 0.0;
-    for (int i = tid; i < a.n_paths; i += 1024) s += exp(a.lw0[i] + a.lw_theta[i] - M);
+    for (int i = tid; i < a.n_paths; i += 1024) s += exp(a.lw0[i] + use_t * a.lw_theta[i] - M);
     red[tid] = s;
     __syncthreads();
     for (int w = 512; w > 0; w >>= 1) {
@@ -193,8 +197,20 @@ __global__ __launch_bounds__(1024) void fpt_train_softmax_kernel(TrainArgs a) {
         __syncthreads();
     }
     const double S = red[0];
-    for (int i = tid; i < a.n_paths; i += 1024) a.c[i] = exp(a.lw0[i] + a.lw_theta[i] - M) / S;
-    if (tid == 0) a.loss[0] = M + log(S) - log(a.n_total);
+    __syncthreads();
+    double ce = 0.0;
+    for (int i = tid; i < a.n_paths; i += 1024) {
+        const double c = exp(a.lw0[i] + use_t * a.lw_theta[i] - M) / S;
+        a.c[i] = c;
+        ce += c * a.lw_theta[i];
+    }
+    red[tid] = ce;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+        if (tid < w) red[tid] += red[tid + w];
+        __syncthreads();
+    }
+    if (tid == 0) a.loss[0] = a.objective == 0 ? M + log(S) - log(a.n_total) : red[0];
 }
 
 // ---------------------------------------------------------------------------

@@ -881,11 +881,12 @@ int pyfpt_proposal_records(const pyfpt_instance *inst, uint64_t seed, const uint
 
 int pyfpt_proposal_loss_grad(const pyfpt_mlp *net, double target_N, double dN, const float *theta,
                              const pyfpt_record *rec, uint64_t n_rec, const uint64_t *rec_off, int32_t n_paths,
-                             const double *lw0, double n_total, double *loss, double *grad, double *lw_theta,
-                             const pyfpt_options *opt) {
+                             const double *lw0, double n_total, int32_t objective, double *loss, double *grad,
+                             double *lw_theta, const pyfpt_options *opt) {
     if (!net || !theta || !rec_off || !lw0 || !loss || !grad || !lw_theta || (n_rec > 0 && !rec))
         return fail(PYFPT_EINVAL, "NULL argument");
     if (n_paths < 1 || n_paths >= (1 << 29)) return fail(PYFPT_EINVAL, "n_paths must be 1 .. 2^29-1");
+    if (objective != 0 && objective != 1) return fail(PYFPT_EINVAL, "objective must be 0 or 1");
     if (!(dN > 0) || !std::isfinite(dN) || !(n_total > 0) || !std::isfinite(target_N))
         return fail(PYFPT_EINVAL, "need finite dN > 0, n_total > 0 and finite target_N");
     int rc = check_offsets(rec_off, n_paths, n_rec);
@@ -914,6 +915,7 @@ int pyfpt_proposal_loss_grad(const pyfpt_mlp *net, double target_N, double dN, c
     ta.rec_off = off.as<uint64_t>();
     ta.n_paths = n_paths;
     ta.n_part = n_part;
+    ta.objective = objective;
     ta.theta = th.as<float>();
     ta.mc = mlp_consts(*net, target_N);
     ta.dN = static_cast<float>(dN);
@@ -945,6 +947,7 @@ int pyfpt_train_proposal(const pyfpt_instance *inst, uint64_t seed, const pyfpt_
         return fail(PYFPT_EINVAL, "need a finite window lo < hi");
     if (!(cfg->lr > 0) || !(cfg->beta1 >= 0 && cfg->beta1 < 1) || !(cfg->beta2 >= 0 && cfg->beta2 < 1) || !(cfg->eps > 0))
         return fail(PYFPT_EINVAL, "bad Adam constants");
+    if (cfg->objective != 0 && cfg->objective != 1) return fail(PYFPT_EINVAL, "objective must be 0 or 1");
     if (cfg->n_sample >= (1ull << 32)) return fail(PYFPT_EINVAL, "n_sample must be < 2^32");
     for (int j = 0; j < NET_N_PARAMS; ++j)
         if (!std::isfinite(theta[j])) return fail(PYFPT_EINVAL, "theta[%d] is not finite", j);
@@ -1080,6 +1083,7 @@ int pyfpt_train_proposal(const pyfpt_instance *inst, uint64_t seed, const pyfpt_
         ta.rec_off = doff.as<uint64_t>();
         ta.n_paths = static_cast<int32_t>(np);
         ta.n_part = n_part;
+        ta.objective = cfg->objective;
         ta.theta = th.as<float>();
         ta.mc = P.inst[0].mlp;
         ta.dN = P.inst[0].c.dN;

@@ -85,3 +85,36 @@ def test_gradient_matches_finite_differences():
         tm = theta.copy(); tm[j] -= h
         fd = (O.loss_grad(mm, tp, rec, rec.lw, 1e4)[0] - O.loss_grad(mm, tm, rec, rec.lw, 1e4)[0]) / (2 * h)
         assert abs(fd - grad[j]) <= 1e-6 * scale + 1e-5 * abs(grad[j]), (j, fd, grad[j])
+
+
+def test_cross_entropy_gradient_and_closed_form():
+    """Objective 1 (cross entropy): the loss is sum_i c_i ln w_theta,i with c_i ~ w_0,i; for a
+    constant candidate c its value follows from the closed form above, and its gradient matches
+    central finite differences."""
+    m = _fixed_model()
+    ids, _ = _short_paths(m, 6000, 11000, 6)
+    rec = O.records(m, 0, ids, 4)
+    c = 0.7
+    v = np.zeros(4481)
+    v[4480] = c
+    net = W.MlpParams(np.zeros(4481, np.float32), out_scale=1.0)
+    mm = O.Model.from_instance(W.c4_instance(net, n_traj=1, stream=m.stream))
+    loss, _, lwt = O.loss_grad(mm, v, rec, rec.lw, 1e4, objective=1)
+    dN = float(np.float32(m.dN))
+    ci = np.exp(rec.lw - rec.lw.max())
+    ci /= ci.sum()
+    want = np.sum(ci * (c * rec.lw + rec.k * dN * (c * c - c) / 2))
+    # the binary32 rounding bound of the constant-candidate closed form, weighted by c_i
+    tol = np.sum(ci * rec.k * 2.0 ** -24 * (dN + np.sqrt(dN)) * (1 + c))
+    assert abs(loss - want) <= tol
+    p = W.c4_params(5, scale=1.5, out_scale=0.8)
+    mm = O.Model.from_instance(W.c4_instance(p, n_traj=1, stream=m.stream))
+    theta = p.values_f32().astype(np.float64)
+    loss, grad, _ = O.loss_grad(mm, theta, rec, rec.lw, 1e4, objective=1)
+    scale = np.max(np.abs(grad))
+    h = 1e-5
+    for j in (5, 200, 300, 4000, 4360, 4420, 4480):
+        tp = theta.copy(); tp[j] += h
+        tm = theta.copy(); tm[j] -= h
+        fd = (O.loss_grad(mm, tp, rec, rec.lw, 1e4, 1)[0] - O.loss_grad(mm, tm, rec, rec.lw, 1e4, 1)[0]) / (2 * h)
+        assert abs(fd - grad[j]) <= 1e-6 * scale + 1e-5 * abs(grad[j]), (j, fd, grad[j])
