@@ -184,9 +184,14 @@ def learned_gain(args):
     train_s = time.perf_counter() - t0
     p1 = W.MlpParams(theta, in_mean=p0.in_mean, in_inv_scale=p0.in_inv_scale, out_scale=1.0, eval_every=4)
     learned = evaluate(dataclasses.replace(inst0, mlp=p1), "learned", block=256, wg_per_cu=1, chunk=1)
-    best = min((f for f in out["fixed"] if f["gpu_s_to_1pct"]), key=lambda f: f["gpu_s_to_1pct"])
-    out.update(learned=learned, train_s=train_s, train_rounds=rep, best_fixed=best["label"],
-               gain=(best["gpu_s_to_1pct"] / learned["gpu_s_to_1pct"]) if learned["gpu_s_to_1pct"] else None)
+    # a fixed bias is a candidate only where its window estimate is trusted by the paper's
+    # n_j > 400 criterion (Sec. 2.1); with fewer runs its error estimate is itself unreliable
+    cands = [f for f in out["fixed"] if f["gpu_s_to_1pct"] and f["count"] > 400]
+    best = min(cands, key=lambda f: f["gpu_s_to_1pct"]) if cands else None
+    lg = learned["gpu_s_to_1pct"]
+    out.update(learned=learned, train_s=train_s, train_rounds=rep, best_fixed=best["label"] if best else None,
+               gain=(best["gpu_s_to_1pct"] / lg) if (best and lg) else None,
+               gain_with_training=(best["gpu_s_to_1pct"] / (lg + train_s)) if (best and lg) else None)
     print(json.dumps(out), flush=True)
 
 
