@@ -151,8 +151,23 @@ typedef struct pyfpt_instance {
  *   log_p[B]           log P_hat_j = lse_w - log(e_{j+1} - e_j) - log n_traj
  *   rel_err_jk[B]      jackknife relative error of P_hat_j (sd over subsets / sqrt J)
  *   rel_err_kish[B]    sqrt(sum w^2/(sum w)^2 - 1/n_traj): delta-method relative error
+ *   log_p_ln[B]        lognormal estimator (Sec. 2.4, eqs. eq_lognormal_mean_maximum_likelihood and
+ *                      eq_lognormal_bin_pdf_reconstrcuted_weighted_maximum_likelihood):
+ *                      log( n_j exp(<ln w>_j + s_j^2/2) / (n_traj (e_{j+1} - e_j)) ), s_j^2 the
+ *                      unbiased sample variance of ln w in the bin (NaN for n_j < 2)
+ *   rel_err_ln_lo[B], rel_err_ln_hi[B]
+ *                      its error (eq. eq_log_normal_bin_pdf_reconstrcuted_error_maximum_likelihood,
+ *                      the Cox interval): P_hat (1 - rel_lo) .. P_hat (1 + rel_hi), rel = |exp(-+u) - 1|,
+ *                      u = sqrt(s^2/n_j + s^4/(2 n_j - 2))
+ *   normal_p[B]        p-value of D'Agostino and Pearson's K^2 normality test of ln w in the bin
+ *                      (skewness test of D'Agostino 1970, kurtosis test of Anscombe and Glynn 1983,
+ *                      K^2 ~ chi^2 with 2 degrees of freedom; NaN for n_j < 8).  The paper accepts
+ *                      the lognormal estimator when every bin's p-value is at least 0.005.
  *   lse_w_all, lse_w2_all, lse_wk, lse_wk2   log sum over all runs of w, w^2, w k, w k^2
  *   sum_k2             sum of k^2 over all runs
+ *   pearson_r          Pearson's correlation coefficient of ln w (equivalently log10 w) with N over
+ *                      the runs that ended (Sec. 3.4: |r| near 1 means a squeezed (N, w) scatter, the
+ *                      criterion for tuning the power p of the bias A_p phi^p); NaN if undefined
  */
 typedef struct pyfpt_result {
     uint64_t *counts;
@@ -165,7 +180,9 @@ typedef struct pyfpt_layout {
     uint64_t count, jk_count, n_traj, total_steps;
     uint64_t lse_w, lse_w2, jk_lse_w, mean_lnw, m2_lnw, m3_lnw, m4_lnw;
     uint64_t log_p, rel_err_jk, rel_err_kish;
+    uint64_t log_p_ln, rel_err_ln_lo, rel_err_ln_hi, normal_p;
     uint64_t lse_w_all, lse_w2_all, lse_wk, lse_wk2, sum_k2;
+    uint64_t pearson_r;
 } pyfpt_layout;
 
 /* Per-trajectory record of runs t with t % stride == 0 and t / stride < n
@@ -237,6 +254,25 @@ int pyfpt_workspace_size(const pyfpt_instance *inst, int32_t n_inst, const pyfpt
  */
 int pyfpt_mlp_forward(const pyfpt_mlp *mlp, double target_N, const float *phi, const float *N, float *r,
                       uint64_t n, void *stream);
+
+/*
+ * Multi-bias reconstruction.  Runs with different bias amplitudes probe different regions of
+ * one P(N) and agree where they overlap (Sec. 3.2 and 3.3); this combines, bin by bin, the
+ * estimates of n_res results that share the same n_bins bins and n_sub.  A result contributes
+ * to a bin only where its estimate is trusted, and contributions are weighted by the inverse
+ * variance of log P_hat:
+ *   estimator 0: naive P_hat (log_p) with the jackknife error rel_err_jk as the error of
+ *                log P; trusted when n_j > 400 (Sec. 2.1) and n_j > exp(sigma^2_lnw) (Sec. 2.4);
+ *   estimator 1: lognormal P_hat (log_p_ln) with u = log(1 + rel_err_ln_hi) as the error of
+ *                log P; trusted when n_j >= 8 and the bin's normality p-value >= 0.005;
+ *   estimator 2: per result, estimator 1 when the result passes the lognormal gate (no bin with
+ *                a defined p-value below 0.005, Sec. 2.4), else estimator 0.
+ * res: n_res results (host or device buffers, as each one's on_device says).  Outputs (host,
+ * n_bins each): log_p (NaN where nothing contributes), err_log (standard error of log P),
+ * n_used (contributing results).  Host arithmetic; EINVAL for bad arguments.
+ */
+int pyfpt_combine(const pyfpt_result *res, int32_t n_res, int32_t n_bins, int32_t n_sub, int32_t estimator,
+                  double *log_p, double *err_log, int32_t *n_used);
 
 /* ---- training of the learned proposal ----
  *

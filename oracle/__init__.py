@@ -361,10 +361,29 @@ class Histogram:
     sum_k: float
     sum_k2: float
     n_per_sub: np.ndarray   # launched runs per jackknife subset
+    s2_lnw: np.ndarray = None      # unbiased sample variance of ln w per row (nan if n < 2)
+    normal_p: np.ndarray = None    # D'Agostino-Pearson p-value of ln w per row (nan if n < 8)
+    pearson_r: float = float("nan")  # Pearson's r of log10 w with N over the ended runs (Sec. 3.4)
 
     # --- estimators ---
     def widths(self):
         return np.diff(self.edges)
+
+    def lognormal(self):
+        """Lognormal estimator of Sec. 2.4: <w_j> = exp(<ln w>_j + s_j^2/2) (eq.
+        eq_lognormal_mean_maximum_likelihood), P_hat_j = n_j <w_j> / (n_total Delta_j) (eq.
+        eq_lognormal_bin_pdf_reconstrcuted_weighted_maximum_likelihood), and the relative error
+        factors |exp(-+u) - 1|, u = sqrt(s^2/n_j + s^4/(2 n_j - 2)) (eq.
+        eq_log_normal_bin_pdf_reconstrcuted_error_maximum_likelihood).  s^2 is the unbiased sample
+        variance.  Returns (log P_hat, rel_lo, rel_hi) per bin, nan where n_j < 2."""
+        B = len(self.edges) - 1
+        n = self.count[:B].astype(np.float64)
+        s2 = self.s2_lnw[:B]
+        with np.errstate(divide="ignore", invalid="ignore"):
+            lp = np.log(n) + self.mean_lnw[:B] + 0.5 * s2 - np.log(self.widths()) - np.log(self.n_traj)
+            u = np.sqrt(s2 / n + s2 * s2 / (2 * n - 2))
+        ok = n >= 2
+        return np.where(ok, lp, np.nan), np.where(ok, -np.expm1(-u), np.nan), np.where(ok, np.expm1(u), np.nan)
 
     def log_p_naive(self):
         """log P_hat_j = log(sum_i w_i / (Delta_j n_total)), n_total = all launched runs."""
@@ -395,6 +414,43 @@ class Histogram:
             return np.exp(2 * self.lse_w[:B] - self.lse_w2[:B])
 
 
+def combine(hists, estimator: int = 2):
+    """Multi-bias reconstruction (Sec. 3.2, 3.3): per bin, the inverse-variance weighted mean of
+    log P_hat over the histograms whose estimate is trusted there.  estimator 0: naive P_hat,
+    error of log P = the jackknife relative error, trusted if n_j > 400 and n_j > exp(sigma^2);
+    1: lognormal P_hat, error u = log(1 + rel_hi), trusted if n_j >= 8 and p >= 0.005; 2: the
+    lognormal estimator for a histogram that passes the gate in every bin with a p-value, else
+    the naive one.  Returns (log_p, err_log, n_used)."""
+    B = len(hists[0].edges) - 1
+    sw = np.zeros(B)
+    swy = np.zeros(B)
+    used = np.zeros(B, np.int32)
+    for h in hists:
+        est = estimator
+        pv = h.normal_p[:B]
+        if est == 2:
+            est = 1 if not np.any(np.isfinite(pv) & (pv < 0.005)) else 0
+        n = h.count[:B].astype(np.float64)
+        if est == 0:
+            y = h.log_p_naive()
+            e = h.jackknife_rel_err()
+            with np.errstate(over="ignore", invalid="ignore"):
+                ok = (n > 400) & (n > np.exp(h.m2_lnw[:B]))
+        else:
+            y, _, hi = h.lognormal()
+            e = np.log1p(hi)
+            with np.errstate(invalid="ignore"):
+                ok = (n >= 8) & np.isfinite(pv) & (pv >= 0.005)
+        with np.errstate(invalid="ignore"):
+            ok &= np.isfinite(y) & np.isfinite(e) & (e > 0)
+        w = np.where(ok, 1.0 / np.where(ok, e, 1.0) ** 2, 0.0)
+        sw += w
+        swy += np.where(ok, w * np.where(ok, y, 0.0), 0.0)
+        used += ok
+    with np.errstate(invalid="ignore", divide="ignore"):
+        return np.where(used > 0, swy / sw, np.nan), np.where(used > 0, 1.0 / np.sqrt(sw), np.nan), used
+
+
 def bin_rows(k: np.ndarray, status: np.ndarray, dN: float, edges: np.ndarray) -> np.ndarray:
     """Row of each run: bin j with e_j < N <= e_{j+1} (N = k dN); B for N <= e_0;
     B+1 for N > e_B; B+2 censored; B+3 escaped."""
@@ -421,6 +477,8 @@ def histogram(tr: Trajectories, dN: float, edges, n_sub: int = 16, n_traj: int |
     jk_count = np.zeros((n_sub, R), np.int64)
     jk_lse_w = np.full((n_sub, R), -np.inf)
     mean = np.full(R, np.nan)
+    s2 = np.full(R, np.nan)
+    normal_p = np.full(R, np.nan)
     m2 = np.full(R, np.nan)
     m3 = np.full(R, np.nan)
     m4 = np.full(R, np.nan)
@@ -441,6 +499,10 @@ def histogram(tr: Trajectories, dN: float, edges, n_sub: int = 16, n_traj: int |
         m2[r] = np.mean(d ** 2)
         m3[r] = np.mean(d ** 3)
         m4[r] = np.mean(d ** 4)
+        if idx.size >= 2:
+            s2[r] = np.var(x, ddof=1)
+        if idx.size >= 8:
+            normal_p[r] = _normaltest_p(x)
         s = sub[idx]
         for q in range(n_sub):
             xs = x[s == q]
@@ -456,4 +518,26 @@ def histogram(tr: Trajectories, dN: float, edges, n_sub: int = 16, n_traj: int |
     return Histogram(edges, n_traj, n_sub, count, lse_w, lse_w2, jk_count, jk_lse_w,
                      mean, m2, m3, m4, int(tr.k.sum()), int(np.sum(tr.status == ST_ENDED)),
                      _lse(tr.lw), _lse(2 * tr.lw), _lse(tr.lw + lnk), _lse(tr.lw + 2 * lnk),
-                     float(kf.sum()), float((kf * kf).sum()), n_per_sub)
+                     float(kf.sum()), float((kf * kf).sum()), n_per_sub, s2, normal_p,
+                     _pearson(tr.lw[tr.status == ST_ENDED] / np.log(10.0), kf[tr.status == ST_ENDED] * dN))
+
+
+def _pearson(x, y) -> float:
+    """Pearson's correlation coefficient (library routine); nan with fewer than two points or
+    no spread."""
+    if x.size < 2 or np.ptp(x) == 0 or np.ptp(y) == 0:
+        return float("nan")
+    return float(np.corrcoef(x, y)[0, 1])
+
+
+def _normaltest_p(x) -> float:
+    """p-value of D'Agostino and Pearson's K^2 test (Sec. 2.4 uses it on ln w), as the library
+    routine computes it; nan when the sample has no spread."""
+    from scipy import stats
+    x = np.asarray(x, np.float64)
+    if np.ptp(x) == 0:
+        return float("nan")
+    import warnings
+    with warnings.catch_warnings():
+        warnings.simplefilter("ignore")
+        return float(stats.normaltest(x).pvalue)

@@ -357,3 +357,186 @@ def sl_modes(model: Model, n_modes: int = 3, lam_max: float | None = None, n_sca
         lams.append(lam)
         amps.append(lam * c * psi_in)
     return Modes(np.array(lams), np.array(amps))
+
+
+# --------------------------------------------------------------------------
+# Cumulants of N and the Edgeworth expansion (App. B).
+#
+# The cumulant generating function K(s, phi) = ln E[exp(s N)] of the first-passage time from
+# phi satisfies L K + (S^2/2)(K')^2 + s = 0 with L = (S^2/2) d^2 + (D + B) d (the backward
+# equation of E[exp(s N)] divided by it), K = 0 at phi_end and K' = 0 at phi_UV.  Order by order
+# in s the cumulants solve the same linear problem with sources built from lower orders:
+#   L k1 = -1,  L k2 = -S^2 k1'^2,  L k3 = -3 S^2 k1' k2',  L k4 = -S^2 (4 k1' k3' + 3 k2'^2).
+# In the integrating-factor form used by `moments` (divide by S^2/2) the sources are
+# 2/S^2, 2 k1'^2, 6 k1' k2' and 8 k1' k3' + 6 k2'^2.
+# --------------------------------------------------------------------------
+@dataclass
+class Cumulants:
+    k1: float
+    k2: float
+    k3: float
+    k4: float
+
+    @property
+    def skewness(self):
+        return self.k3 / self.k2 ** 1.5
+
+    @property
+    def excess_kurtosis(self):
+        return self.k4 / self.k2 ** 2
+
+
+def cumulants(model: Model, biased: bool = False, n_grid: int = 400001, phi=None) -> Cumulants:
+    """The first four cumulants of N from phi (default phi_in), Richardson-extrapolated over grids
+    of n and n/2 cells like `moments`."""
+    phi = model.phi_in if phi is None else phi
+
+    def solve(n):
+        top = _top(model, biased)
+        if model.pot != POT_FLAT and model.phi_end > 0:
+            x = model.phi_end * np.exp(np.linspace(0.0, math.log(top / model.phi_end), n))
+        else:
+            x = np.linspace(model.phi_end, top, n)
+        D, S, B = drift_noise(model, x, biased)
+        psi_p = 2.0 * (D + B) / S ** 2
+        xm = 0.5 * (x[1:] + x[:-1])
+        Dm, Sm, Bm = drift_noise(model, xm, biased)
+        psi_pm = 2.0 * (Dm + Bm) / Sm ** 2
+        J1 = _green_derivative(x, psi_p, psi_pm, 2.0 / S ** 2)
+        J2 = _green_derivative(x, psi_p, psi_pm, 2.0 * J1 ** 2)
+        J3 = _green_derivative(x, psi_p, psi_pm, 6.0 * J1 * J2)
+        J4 = _green_derivative(x, psi_p, psi_pm, 8.0 * J1 * J3 + 6.0 * J2 ** 2)
+        return [float(np.interp(phi, x, _trapz_cum(x, J))) for J in (J1, J2, J3, J4)]
+
+    a = solve(n_grid)
+    b = solve((n_grid - 1) // 2 + 1)
+    return Cumulants(*[ai + (ai - bi) / 3.0 for ai, bi in zip(a, b)])
+
+
+def hermite_he(n: int, x):
+    """Probabilists' Hermite polynomials He_3, He_4, He_6 (He_3 = x^3 - 3x: the appendix prints
+    x^2 - 1, which is not orthogonal to He_1 under the Gaussian weight)."""
+    x = np.asarray(x, np.float64)
+    if n == 3:
+        return x ** 3 - 3 * x
+    if n == 4:
+        return x ** 4 - 6 * x ** 2 + 3
+    if n == 6:
+        return x ** 6 - 15 * x ** 4 + 45 * x ** 2 - 15
+    raise ValueError(n)
+
+
+def gaussian_pdf(N, mu: float, sigma: float):
+    z = (np.asarray(N, np.float64) - mu) / sigma
+    return np.exp(-0.5 * z * z) / (sigma * math.sqrt(2 * math.pi))
+
+
+def edgeworth_pdf(N, mu: float, sigma: float, gamma: float, kappa: float):
+    """App. B, eq. eq_edgeworth_expansion: the Gaussian times
+    1 + gamma/6 He_3 + kappa/24 He_4 + gamma^2/72 He_6 of z = (N - mu)/sigma."""
+    z = (np.asarray(N, np.float64) - mu) / sigma
+    corr = 1 + gamma / 6 * hermite_he(3, z) + kappa / 24 * hermite_he(4, z) + gamma ** 2 / 72 * hermite_he(6, z)
+    return gaussian_pdf(N, mu, sigma) * corr
+
+
+def edgeworth_for(model: Model, n_grid: int = 400001):
+    """(mu, sigma, gamma, kappa) of the target process of `model` from its cumulants."""
+    c = cumulants(model, biased=False, n_grid=n_grid)
+    return c.k1, math.sqrt(c.k2), c.skewness, c.excess_kurtosis
+
+
+# --------------------------------------------------------------------------
+# Characteristic function of N for quadratic inflation (App. A) with confluent hypergeometric
+# functions, its poles and residues, and the branch-cut integral without a wall.
+#   v(phi) = V/(24 pi^2) = v0 phi^2, v0 = m^2/(48 pi^2);  alpha(t) = sqrt(1 - 4 i t / v0);
+#   f = v^((1+alpha)/4) 1F1((-1-alpha)/4; 1 - alpha/2; -1/v),
+#   g = v^((1-alpha)/4) 1F1((-1+alpha)/4; 1 + alpha/2; -1/v);
+#   A = f'(phi_UV)/g'(phi_UV), B = f(phi_end)/g(phi_end);
+#   chi = B/(B - A) f/f_end - A/(B - A) g/g_end (eq. eq:characteristicFunction:generic).
+# mpmath evaluates everything at `dps` digits.
+# --------------------------------------------------------------------------
+def _fg(alpha, v, deriv: bool, mp):
+    """f and g (or their phi-derivatives times phi, using d/dphi = (2v/phi) d/dv) at v."""
+    def one(s):
+        a = (-1 - s * alpha) / 4
+        b = 1 - s * alpha / 2
+        z = -1 / v
+        pref = v ** ((1 + s * alpha) / 4)
+        F = mp.hyp1f1(a, b, z)
+        if not deriv:
+            return pref * F
+        dF = (a / b) * mp.hyp1f1(a + 1, b + 1, z)          # d/dz 1F1(a;b;z)
+        # d/dv [v^p F(-1/v)] = p v^(p-1) F + v^p F'(z) / v^2, times 2v (phi d/dphi)
+        p = (1 + s * alpha) / 4
+        return 2 * v * (p * v ** (p - 1) * F + pref * dF / v ** 2)
+    return one(1), one(-1)
+
+
+def char_function(t, model: Model, phi=None, dps: int = 50):
+    """chi(t, phi) of the quadratic model with a reflecting wall (complex t allowed)."""
+    import mpmath as mp
+    mp.mp.dps = dps
+    phi = model.phi_in if phi is None else phi
+    v0 = mp.mpf(model.m) ** 2 / (48 * mp.pi ** 2)
+    alpha = mp.sqrt(1 - 4j * mp.mpmathify(t) / v0)
+    v = lambda x: v0 * mp.mpf(x) ** 2
+    fe, ge = _fg(alpha, v(model.phi_end), False, mp)
+    fu, gu = _fg(alpha, v(model.phi_uv), True, mp)
+    f, g = _fg(alpha, v(phi), False, mp)
+    A = fu / gu
+    B = fe / ge
+    return B / (B - A) * f / fe - A / (B - A) * g / ge
+
+
+def _vfun(model: Model, mp):
+    v0 = mp.mpf(model.m) ** 2 / (48 * mp.pi ** 2)
+    return v0, (lambda x: v0 * mp.mpf(x) ** 2)
+
+
+def pole_q(lam, model: Model, dps: int = 50) -> float:
+    """A real function of Lambda whose zeros above v0/4 are the poles Lambda_n = i t_n of chi.
+    There alpha is imaginary, f and g are complex conjugates, |A| = |B| = 1, and A = B exactly
+    when g'(phi_UV) and g(phi_end) have the same phase modulo pi: this returns the sine of
+    their phase difference."""
+    import mpmath as mp
+    mp.mp.dps = dps
+    v0, v = _vfun(model, mp)
+    alpha = mp.sqrt(mp.mpc(1 - 4 * mp.mpf(lam) / v0))
+    _, ge = _fg(alpha, v(model.phi_end), False, mp)
+    _, gu = _fg(alpha, v(model.phi_uv), True, mp)
+    z = gu * mp.conj(ge)
+    return float(mp.im(z) / abs(z))
+
+
+def char_poles(model: Model, lam_brackets, dps: int = 50):
+    """Poles Lambda_n inside the given brackets (roots of pole_q) with the residues
+    a_n(phi_in) = lim (Lambda_n - i t) chi(t) (eq. eq_appendix_residual_numerical), taken on
+    t = -i L as the mean of (Lambda_n - L) chi(-i L) at L = Lambda_n (1 -+ 1e-12)."""
+    import mpmath as mp
+    mp.mp.dps = dps
+    out = []
+    for lo, hi in lam_brackets:
+        root = mp.findroot(lambda L: pole_q(L, model, dps), (mp.mpf(lo), mp.mpf(hi)), solver="illinois",
+                           tol=mp.mpf(10) ** (-2 * dps // 3))
+        eps = root * mp.mpf("1e-12")
+        vals = [(root - L) * char_function(-1j * L, model, dps=dps) for L in (root - eps, root + eps)]
+        out.append((float(root), float(mp.re(sum(vals) / 2))))
+    return out
+
+
+def char_cumulants(model: Model, h: float = None, dps: int = 60, n_fit: int = 9):
+    """The first four cumulants of N as the Taylor coefficients of ln chi(-i s) = ln E[exp(s N)]
+    at s = 0, from a polynomial fit through points +-h, +-2h, ... (chi's formula has a removable
+    singularity at s = 0 itself)."""
+    import mpmath as mp
+    mp.mp.dps = dps
+    if h is None:
+        h = 1e-4 / max(1.0, 10.0)
+    pts = [mp.mpf(h) * k for k in range(-n_fit, n_fit + 1) if k != 0]
+    vals = [mp.log(mp.re(char_function(-1j * x, model, dps=dps))) for x in pts]
+    deg = 8
+    A = mp.matrix([[x ** j for j in range(deg + 1)] for x in pts])
+    b = mp.matrix(vals)
+    c = mp.lu_solve(A.T * A, A.T * b)
+    fac = [1, 1, 2, 6, 24]
+    return Cumulants(*[float(c[n] * fac[n]) for n in (1, 2, 3, 4)])

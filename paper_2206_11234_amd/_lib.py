@@ -55,7 +55,8 @@ class pyfpt_layout(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in (
         "n_counts", "n_values", "count", "jk_count", "n_traj", "total_steps",
         "lse_w", "lse_w2", "jk_lse_w", "mean_lnw", "m2_lnw", "m3_lnw", "m4_lnw",
-        "log_p", "rel_err_jk", "rel_err_kish", "lse_w_all", "lse_w2_all", "lse_wk", "lse_wk2", "sum_k2")]
+        "log_p", "rel_err_jk", "rel_err_kish", "log_p_ln", "rel_err_ln_lo", "rel_err_ln_hi", "normal_p",
+        "lse_w_all", "lse_w2_all", "lse_wk", "lse_wk2", "sum_k2", "pearson_r")]
 
 
 class pyfpt_dump(ctypes.Structure):
@@ -92,7 +93,7 @@ class pyfpt_train_report(ctypes.Structure):
 
 # every entry point declared in include/pyfpt.h
 EXPORTS = ("pyfpt_result_layout", "pyfpt_run", "pyfpt_run_batch", "pyfpt_workspace_size",
-           "pyfpt_mlp_forward", "pyfpt_proposal_records", "pyfpt_proposal_loss_grad", "pyfpt_train_proposal",
+           "pyfpt_mlp_forward", "pyfpt_combine", "pyfpt_proposal_records", "pyfpt_proposal_loss_grad", "pyfpt_train_proposal",
            "pyfpt_device_cus", "pyfpt_last_error")
 
 _lib = None
@@ -124,6 +125,8 @@ def load() -> ctypes.CDLL:
     L.pyfpt_mlp_forward.argtypes = [P(pyfpt_mlp), ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,
                                     ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
     vp = ctypes.c_void_p
+    L.pyfpt_combine.argtypes = [P(pyfpt_result), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                vp, vp, vp]
     L.pyfpt_proposal_records.argtypes = [P(pyfpt_instance), ctypes.c_uint64, vp, ctypes.c_int32, ctypes.c_int32, vp, vp,
                                          vp, vp, vp, P(pyfpt_options)]
     L.pyfpt_proposal_loss_grad.argtypes = [P(pyfpt_mlp), ctypes.c_double, ctypes.c_double, vp, vp, ctypes.c_uint64, vp,

@@ -109,6 +109,29 @@ class Result:
         return self._v(self.lay.rel_err_kish, self.n_bins)
 
     @property
+    def log_p_ln(self):
+        return self._v(self.lay.log_p_ln, self.n_bins)
+
+    @property
+    def rel_err_ln_lo(self):
+        return self._v(self.lay.rel_err_ln_lo, self.n_bins)
+
+    @property
+    def rel_err_ln_hi(self):
+        return self._v(self.lay.rel_err_ln_hi, self.n_bins)
+
+    @property
+    def normal_p(self):
+        return self._v(self.lay.normal_p, self.n_bins)
+
+    def lognormal_accepted(self, threshold: float = 0.005, min_count: int = 8) -> bool:
+        """The paper's gate (Sec. 2.4): the lognormal estimator is used when no bin with a
+        defined normality p-value falls below the threshold (0.5 %)."""
+        p = self.normal_p[self.count[:self.n_bins] >= min_count]
+        p = p[np.isfinite(p)]
+        return bool(np.all(p >= threshold))
+
+    @property
     def lse_w_all(self):
         return float(self.values[self.lay.lse_w_all])
 
@@ -127,6 +150,10 @@ class Result:
     @property
     def sum_k2(self):
         return float(self.values[self.lay.sum_k2])
+
+    @property
+    def pearson_r(self):
+        return float(self.values[self.lay.pearson_r])
 
     def ess(self):
         with np.errstate(invalid="ignore"):
@@ -298,6 +325,25 @@ def device_cus() -> int:
     n = ctypes.c_int32(0)
     L.check(L.load().pyfpt_device_cus(ctypes.byref(n)))
     return int(n.value)
+
+
+def combine(results, estimator: int = 2):
+    """Multi-bias reconstruction (pyfpt_combine): per-bin inverse-variance combination in
+    log P of results sharing the same bins.  Returns (log_p, err_log, n_used)."""
+    n = len(results)
+    B = results[0].n_bins
+    arr = (L.pyfpt_result * n)()
+    keep = []
+    for i, r in enumerate(results):
+        c = np.ascontiguousarray(r.counts, np.uint64)
+        v = np.ascontiguousarray(r.values, np.float64)
+        keep += [c, v]
+        arr[i] = L.pyfpt_result(c.ctypes.data, v.ctypes.data, 0)
+    lp = np.zeros(B)
+    el = np.zeros(B)
+    nu = np.zeros(B, np.int32)
+    L.check(L.load().pyfpt_combine(arr, n, B, results[0].n_sub, int(estimator), _ptr(lp), _ptr(el), _ptr(nu)))
+    return lp, el, nu
 
 
 # ---------------------------------------------------------------------------

@@ -18,7 +18,7 @@ struct InstDev {
     uint32_t row_base;    // first row of this instance in the per-workgroup table
     uint32_t thr_base;    // first integer bin threshold of this instance
     uint32_t dump_slot;   // caller's instance index
-    uint32_t pad0;
+    uint32_t k_center;    // expected step count: centre of k in the correlation sums
     uint64_t n_traj;
     uint64_t v_begin;     // first id of this instance in the shared queue
 };
@@ -31,7 +31,8 @@ struct TableLayout {
     uint32_t n_inst;
     uint32_t slice_bytes;
     // binary64 arrays
-    uint32_t off_scal;    // [n_inst][8]: lse_w_all, lse_w2_all, lse_wk, lse_wk2, sum_k2, (u64) steps, pad, pad
+    uint32_t off_scal;    // [n_inst][16]: lse_w_all, lse_w2_all, lse_wk, lse_wk2, sum_k2, steps, then over the
+                          // ended runs: n, sum x, sum x^2, sum y, sum y^2, sum xy (x = ln w, y = k - k_center), pad
     uint32_t off_jk_lse;  // [J][n_rows]
     uint32_t off_lse_w2;  // [n_rows]
     uint32_t off_shift;   // [n_rows]
@@ -89,7 +90,9 @@ struct ResultLayout {
     uint64_t count, jk_count, n_traj, total_steps;
     uint64_t lse_w, lse_w2, jk_lse_w, mean_lnw, m2_lnw, m3_lnw, m4_lnw;
     uint64_t log_p, rel_err_jk, rel_err_kish;
+    uint64_t log_p_ln, rel_err_ln_lo, rel_err_ln_hi, normal_p;
     uint64_t lse_w_all, lse_w2_all, lse_wk, lse_wk2, sum_k2;
+    uint64_t pearson_r;
 };
 
 __host__ __device__ inline ResultLayout result_layout(uint32_t n_bins, uint32_t n_sub) {
@@ -112,11 +115,16 @@ __host__ __device__ inline ResultLayout result_layout(uint32_t n_bins, uint32_t 
     L.log_p = v; v += B;
     L.rel_err_jk = v; v += B;
     L.rel_err_kish = v; v += B;
+    L.log_p_ln = v; v += B;
+    L.rel_err_ln_lo = v; v += B;
+    L.rel_err_ln_hi = v; v += B;
+    L.normal_p = v; v += B;
     L.lse_w_all = v++;
     L.lse_w2_all = v++;
     L.lse_wk = v++;
     L.lse_wk2 = v++;
     L.sum_k2 = v++;
+    L.pearson_r = v++;
     L.n_values = v;
     return L;
 }

@@ -85,7 +85,7 @@ __device__ __forceinline__ void init_table(unsigned char *base, const TableLayou
         const uint32_t off = i * 8;
         unsigned long long v = 0ull;
         if (off < L.off_jk_lse) {
-            const uint32_t f = ((off - L.off_scal) / 8) & 7u;
+            const uint32_t f = ((off - L.off_scal) / 8) & 15u;
             v = (f < 4) ? FPT_NEG_INF_BITS : 0ull;
         } else if (off < L.off_shift) {
             v = FPT_NEG_INF_BITS;           // jk_lse, lse_w2
@@ -122,7 +122,7 @@ __device__ __forceinline__ void acc_reset(LaneAcc &a, int inst) {
 }
 
 __device__ __forceinline__ void acc_commit_direct(const Tab &T, const LaneAcc &a) {
-    double *s = T.scal + static_cast<size_t>(a.inst) * 8;
+    double *s = T.scal + static_cast<size_t>(a.inst) * 16;
     atomic_lse(s + 0, a.w);
     atomic_lse(s + 1, a.w2);
     atomic_lse(s + 2, a.wk);
@@ -149,7 +149,7 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
 
     // lane state
     StepConsts C{};
-    uint32_t stream = 0, n_bins = 0, row_base = 0, thr_base = 0, dump_slot = 0;
+    uint32_t stream = 0, n_bins = 0, row_base = 0, thr_base = 0, dump_slot = 0, k_center = 0;
     int cur_inst = -1;
     float phi = 0.0f;
     uint32_t k = 0;
@@ -207,6 +207,7 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
                         row_base = I.row_base;
                         thr_base = I.thr_base;
                         dump_slot = I.dump_slot;
+                        k_center = I.k_center;
                         if constexpr (BIAS == BIAS_MLP) mc = I.mlp;
                         cur_inst = ii;
                     }
@@ -284,6 +285,17 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
             atomic_add_f64(&T.s2[row], d2);
             atomic_add_f64(&T.s3[row], d2 * d);
             atomic_add_f64(&T.s4[row], d2 * d2);
+            if (st == ST_ENDED) {
+                // correlation of ln w with N over the ended runs (Sec. 3.4)
+                double *sc = T.scal + static_cast<size_t>(cur_inst) * 16;
+                const double y = static_cast<double>(static_cast<int64_t>(k) - static_cast<int64_t>(k_center));
+                atomic_add_f64(sc + 6, 1.0);
+                atomic_add_f64(sc + 7, lw);
+                atomic_add_f64(sc + 8, lw * lw);
+                atomic_add_f64(sc + 9, y);
+                atomic_add_f64(sc + 10, y * y);
+                atomic_add_f64(sc + 11, lw * y);
+            }
             // instance-wide sums in lane registers
             const double kd = static_cast<double>(k);
             const double lk = log(kd);
@@ -434,12 +446,13 @@ __global__ __launch_bounds__(256) void fpt_merge_kernel(MergeArgs a) {
     } else if (tid < J * RT + RT + static_cast<uint32_t>(a.n_inst)) {
         const int i = static_cast<int>(tid - J * RT - RT);
         double f[4] = {-INFINITY, -INFINITY, -INFINITY, -INFINITY};
-        double k2 = 0.0, steps = 0.0;
+        double k2 = 0.0, steps = 0.0, ps[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (int w = 0; w < a.n_wg; ++w) {
-            const double *sc = reinterpret_cast<const double *>(a.slices + static_cast<size_t>(w) * L.slice_bytes + L.off_scal) + static_cast<size_t>(i) * 8;
+            const double *sc = reinterpret_cast<const double *>(a.slices + static_cast<size_t>(w) * L.slice_bytes + L.off_scal) + static_cast<size_t>(i) * 16;
             for (int q = 0; q < 4; ++q) f[q] = lse2(f[q], sc[q]);
             k2 += sc[4];
             steps += sc[5];
+            for (int q = 0; q < 6; ++q) ps[q] += sc[6 + q];
         }
         const MergeInst m = a.mi[i];
         const ResultLayout RL = result_layout(m.n_bins, J);
@@ -449,9 +462,70 @@ __global__ __launch_bounds__(256) void fpt_merge_kernel(MergeArgs a) {
         V[RL.lse_wk] = f[2];
         V[RL.lse_wk2] = f[3];
         V[RL.sum_k2] = k2;
+        {
+            // Pearson's r of ln w with N over the ended runs (equal to that of log10 w with N)
+            const double n = ps[0];
+            const double mx = ps[1] / n, my = ps[3] / n;
+            const double cxy = ps[5] / n - mx * my;
+            const double vx = ps[2] / n - mx * mx, vy = ps[4] / n - my * my;
+            V[RL.pearson_r] = (n >= 2.0 && vx > 0.0 && vy > 0.0) ? cxy / sqrt(vx * vy) : NAN;
+        }
         a.counts[m.counts_off + RL.n_traj] = m.n_traj;
         a.counts[m.counts_off + RL.total_steps] = static_cast<uint64_t>(steps);
     }
+}
+
+// D'Agostino and Pearson's omnibus K^2 test of normality from the sample skewness g1 = m3/m2^1.5
+// and kurtosis b2 = m4/m2^2 (population central moments) of n values: the skewness is mapped to a
+// standard normal by D'Agostino's (1970) Johnson S_U transformation, the kurtosis by Anscombe and
+// Glynn's (1983) Wilson-Hilferty-type transformation, and K^2 = Z1^2 + Z2^2 is chi^2 with two
+// degrees of freedom, so p = exp(-K^2/2).
+__device__ double dagostino_pearson_p(double n, double g1, double b2) {
+    // skewness
+    const double y = g1 * sqrt((n + 1.0) * (n + 3.0) / (6.0 * (n - 2.0)));
+    const double beta2 = 3.0 * (n * n + 27.0 * n - 70.0) * (n + 1.0) * (n + 3.0) /
+                         ((n - 2.0) * (n + 5.0) * (n + 7.0) * (n + 9.0));
+    const double w2 = -1.0 + sqrt(2.0 * (beta2 - 1.0));
+    const double delta = 1.0 / sqrt(0.5 * log(w2));
+    const double alpha = sqrt(2.0 / (w2 - 1.0));
+    const double z1 = delta * asinh(y / alpha);
+    // kurtosis
+    const double e = 3.0 * (n - 1.0) / (n + 1.0);
+    const double var = 24.0 * n * (n - 2.0) * (n - 3.0) / ((n + 1.0) * (n + 1.0) * (n + 3.0) * (n + 5.0));
+    const double x = (b2 - e) / sqrt(var);
+    const double sb1 = 6.0 * (n * n - 5.0 * n + 2.0) / ((n + 7.0) * (n + 9.0)) *
+                       sqrt(6.0 * (n + 3.0) * (n + 5.0) / (n * (n - 2.0) * (n - 3.0)));
+    const double A = 6.0 + 8.0 / sb1 * (2.0 / sb1 + sqrt(1.0 + 4.0 / (sb1 * sb1)));
+    const double den = 1.0 + x * sqrt(2.0 / (A - 4.0));
+    if (den == 0.0) return NAN;
+    const double z2 = ((1.0 - 2.0 / (9.0 * A)) - cbrt((1.0 - 2.0 / A) / den)) / sqrt(2.0 / (9.0 * A));
+    return exp(-0.5 * (z1 * z1 + z2 * z2));
+}
+
+// Lognormal estimator of one bin (Sec. 2.4): <w> = exp(<ln w> + s^2/2) with s^2 the unbiased
+// sample variance of ln w; P_hat = n_j <w> / (n_traj width); its Cox interval
+// P_hat exp(+-u), u = sqrt(s^2/n + s^4/(2n - 2)); and the normality p-value of ln w.
+// log_norm = log(width) + log(n_traj).
+__device__ void lognormal_bin(double *V, const ResultLayout &RL, uint32_t lr, uint64_t cnt, double log_norm) {
+    double lp = NAN, lo = NAN, hi = NAN, pv = NAN;
+    if (cnt >= 2) {
+        const double n = static_cast<double>(cnt);
+        const double c2 = V[RL.m2_lnw + lr];
+        const double s2 = c2 * n / (n - 1.0);
+        lp = log(n) + V[RL.mean_lnw + lr] + 0.5 * s2 - log_norm;
+        const double u = sqrt(s2 / n + s2 * s2 / (2.0 * n - 2.0));
+        hi = expm1(u);
+        lo = -expm1(-u);
+        if (cnt >= 8 && c2 > 0.0) {
+            const double g1 = V[RL.m3_lnw + lr] / (c2 * sqrt(c2));
+            const double b2 = V[RL.m4_lnw + lr] / (c2 * c2);
+            pv = dagostino_pearson_p(n, g1, b2);
+        }
+    }
+    V[RL.log_p_ln + lr] = lp;
+    V[RL.rel_err_ln_lo + lr] = lo;
+    V[RL.rel_err_ln_hi + lr] = hi;
+    V[RL.normal_p + lr] = pv;
 }
 
 __global__ __launch_bounds__(256) void fpt_finalize_kernel(MergeArgs a) {
@@ -489,6 +563,7 @@ __global__ __launch_bounds__(256) void fpt_finalize_kernel(MergeArgs a) {
         const double k2 = exp(V[RL.lse_w2 + lr] - 2.0 * l) - 1.0 / nt;
         V[RL.rel_err_kish + lr] = (cnt == 0) ? NAN : sqrt(fmax(k2, 0.0));
         if (cnt == 0) V[RL.rel_err_jk + lr] = NAN;
+        lognormal_bin(V, RL, lr, cnt, log(width) + log(nt));
     }
 }
 

@@ -293,6 +293,7 @@ int prepare(const pyfpt_instance *ins, int n_inst, Prepared &P) {
         D.row_base = rows;
         D.thr_base = thr_base;
         D.dump_slot = static_cast<uint32_t>(i);
+        D.k_center = static_cast<uint32_t>(std::min(expected_steps(I, k_max), 4294967295.0));
         D.n_traj = I.n_traj;
         for (int j = 0; j <= I.bins.n_bins; ++j) {
             P.thr.push_back(threshold(I.bins.edges[j], I.dN));
@@ -334,7 +335,7 @@ int prepare(const pyfpt_instance *ins, int n_inst, Prepared &P) {
     L.n_inst = static_cast<uint32_t>(n_inst);
     size_t off = 0;
     L.off_scal = 0;
-    off = align_up(static_cast<size_t>(n_inst) * 64, 16);
+    off = align_up(static_cast<size_t>(n_inst) * 128, 16);
     L.off_jk_lse = static_cast<uint32_t>(off);
     off += static_cast<size_t>(P.n_sub) * rows * 8;
     L.off_lse_w2 = static_cast<uint32_t>(off);
@@ -763,11 +764,16 @@ int pyfpt_result_layout(int32_t n_bins, int32_t n_sub, pyfpt_layout *out) {
     out->log_p = L.log_p;
     out->rel_err_jk = L.rel_err_jk;
     out->rel_err_kish = L.rel_err_kish;
+    out->log_p_ln = L.log_p_ln;
+    out->rel_err_ln_lo = L.rel_err_ln_lo;
+    out->rel_err_ln_hi = L.rel_err_ln_hi;
+    out->normal_p = L.normal_p;
     out->lse_w_all = L.lse_w_all;
     out->lse_w2_all = L.lse_w2_all;
     out->lse_wk = L.lse_wk;
     out->lse_wk2 = L.lse_wk2;
     out->sum_k2 = L.sum_k2;
+    out->pearson_r = L.pearson_r;
     return PYFPT_OK;
 }
 
@@ -842,6 +848,68 @@ int pyfpt_mlp_forward(const pyfpt_mlp *mlp, double target_N, const float *phi, c
     c.target_N = static_cast<float>(target_N);
     HIP_TRY(launch_mlp_forward(static_cast<const uint16_t *>(mlp->params), c, phi, N, r, n,
                                static_cast<hipStream_t>(stream)), "launch mlp forward");
+    return PYFPT_OK;
+}
+
+int pyfpt_combine(const pyfpt_result *res, int32_t n_res, int32_t n_bins, int32_t n_sub, int32_t estimator,
+                  double *log_p, double *err_log, int32_t *n_used) {
+    if (!res || !log_p || !err_log || !n_used || n_res < 1) return fail(PYFPT_EINVAL, "NULL argument or n_res < 1");
+    if (estimator < 0 || estimator > 2) return fail(PYFPT_EINVAL, "estimator must be 0, 1 or 2");
+    if (n_bins < 1) return fail(PYFPT_EINVAL, "n_bins must be >= 1");
+    if (n_sub == 0) n_sub = kDefaultNsub;
+    if (n_sub < 2 || n_sub > 64) return fail(PYFPT_EINVAL, "n_sub must be 0 or 2..64");
+    const ResultLayout L = result_layout(static_cast<uint32_t>(n_bins), static_cast<uint32_t>(n_sub));
+    const uint32_t B = static_cast<uint32_t>(n_bins);
+    std::vector<double> sw(B, 0.0), swy(B, 0.0);
+    std::fill(n_used, n_used + B, 0);
+    std::vector<uint64_t> cbuf;
+    std::vector<double> vbuf;
+    for (int32_t i = 0; i < n_res; ++i) {
+        if (!res[i].counts || !res[i].values) return fail(PYFPT_EINVAL, "result %d has NULL buffers", i);
+        const uint64_t *C = static_cast<const uint64_t *>(res[i].counts);
+        const double *V = static_cast<const double *>(res[i].values);
+        if (res[i].on_device) {
+            cbuf.resize(L.n_counts);
+            vbuf.resize(L.n_values);
+            HIP_TRY(hipMemcpy(cbuf.data(), C, 8 * L.n_counts, hipMemcpyDeviceToHost), "download counts");
+            HIP_TRY(hipMemcpy(vbuf.data(), V, 8 * L.n_values, hipMemcpyDeviceToHost), "download values");
+            C = cbuf.data();
+            V = vbuf.data();
+        }
+        int est = estimator;
+        if (est == 2) {
+            bool gate = true;
+            for (uint32_t j = 0; j < B; ++j) {
+                const double p = V[L.normal_p + j];
+                if (std::isfinite(p) && p < 0.005) gate = false;
+            }
+            est = gate ? 1 : 0;
+        }
+        for (uint32_t j = 0; j < B; ++j) {
+            const double n = static_cast<double>(C[L.count + j]);
+            double y = NAN, e = NAN;
+            bool ok = false;
+            if (est == 0) {
+                y = V[L.log_p + j];
+                e = V[L.rel_err_jk + j];
+                ok = n > 400.0 && n > std::exp(V[L.m2_lnw + j]);
+            } else {
+                y = V[L.log_p_ln + j];
+                e = std::log1p(V[L.rel_err_ln_hi + j]);
+                const double p = V[L.normal_p + j];
+                ok = n >= 8.0 && std::isfinite(p) && p >= 0.005;
+            }
+            if (!ok || !std::isfinite(y) || !std::isfinite(e) || !(e > 0)) continue;
+            const double w = 1.0 / (e * e);
+            sw[j] += w;
+            swy[j] += w * y;
+            n_used[j] += 1;
+        }
+    }
+    for (uint32_t j = 0; j < B; ++j) {
+        log_p[j] = n_used[j] ? swy[j] / sw[j] : NAN;
+        err_log[j] = n_used[j] ? 1.0 / std::sqrt(sw[j]) : NAN;
+    }
     return PYFPT_OK;
 }
 

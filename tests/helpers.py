@@ -41,6 +41,10 @@ def assert_histogram_matches(res, h, rel=1e-12):
         ok, _ = close_lse([getattr(res, name)], [getattr(h, name)], rel)
         assert ok, (name, getattr(res, name), getattr(h, name))
     assert abs(res.sum_k2 - h.sum_k2) <= 1e-12 * h.sum_k2
+    if np.isnan(h.pearson_r):
+        assert np.isnan(res.pearson_r)
+    else:
+        assert abs(res.pearson_r - h.pearson_r) <= 1e-9, (res.pearson_r, h.pearson_r)
     # moments of ln w per row (population central moments)
     nz = h.count > 0
     assert np.all(np.isnan(res.mean_lnw[~nz]))
@@ -63,6 +67,20 @@ def assert_histogram_matches(res, h, rel=1e-12):
     kish = np.sqrt(np.maximum(h.kish_rel_err2(), 0))
     f3 = np.isfinite(kish) & (h.count[:B] > 0)
     assert np.all(np.abs(res.rel_err_kish[f3] - kish[f3]) <= 1e-8 * np.maximum(1e-3, kish[f3]) + 1e-7)
+    # lognormal estimator and normality gate (Sec. 2.4); the GPU takes them from the merged
+    # shifted power sums, the oracle from the runs themselves
+    lp_ln, lo, hi = h.lognormal()
+    f4 = np.isfinite(lp_ln)
+    assert np.array_equal(np.isfinite(res.log_p_ln), f4)
+    assert np.all(np.abs(res.log_p_ln[f4] - lp_ln[f4]) <= 1e-8 * np.maximum(1, np.abs(lp_ln[f4])))
+    assert np.all(np.abs(res.rel_err_ln_hi[f4] - hi[f4]) <= 1e-7 * hi[f4] + 1e-12)
+    assert np.all(np.abs(res.rel_err_ln_lo[f4] - lo[f4]) <= 1e-7 * lo[f4] + 1e-12)
+    pv = h.normal_p[:B]
+    f5 = np.isfinite(pv)
+    assert np.array_equal(np.isfinite(res.normal_p), f5), (np.nonzero(np.isfinite(res.normal_p) != f5)[0][:5])
+    # the p-value depends on the third and fourth moments (agreeing to ~1e-7 relative)
+    bad = np.nonzero(~(np.abs(res.normal_p[f5] - pv[f5]) <= 1e-4 * pv[f5] + 1e-9))[0]
+    assert bad.size == 0, ("normal_p", res.normal_p[f5][bad][:5], pv[f5][bad][:5])
 
 
 def assert_dump_matches(dump, tr):
