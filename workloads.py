@@ -185,6 +185,15 @@ def c5(n_traj: int = 1_000_000_000) -> Instance:
                     dN=1e-4, n_traj=n_traj, k_max=kmax, edges=log_edges(mu - 6 * sig, mu + 40 * sig, 500))
 
 
+def c5_multi(amplitudes=(0.0, 1.0, 2.0, 3.0, 4.0, 5.0, 6.0), n_total: int = 1_000_000_000):
+    """The large bump-potential run as a multi-bias batch: the runs split evenly over
+    noise-scaled amplitudes (A = 0 is direct sampling), one noise stream per amplitude, the same
+    500 bins."""
+    base = c5(n_total // len(amplitudes))
+    return [replace(base, name=f"C5_A{A:g}", bias=BIAS_NOISE_SCALED if A else BIAS_NONE, A=A, stream=i)
+            for i, A in enumerate(amplitudes)]
+
+
 def paper_diffusion(A: float, n_traj: int = 200_000, stream: int = 0) -> Instance:
     """The diffusion-dominated validation case of Sec. 3.1 (Fig. 3): m = 1,
     phi_in = phi_UV = sqrt 42, A in {0, 0.4, 0.8}, 2e5 runs each.  dN is not stated
