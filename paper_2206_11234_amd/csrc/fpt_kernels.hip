@@ -133,7 +133,9 @@ __device__ __forceinline__ void acc_commit_direct(const Tab &T, const LaneAcc &a
 
 extern __shared__ __align__(16) unsigned char fpt_lds[];
 
-template <int POT, int BIAS, bool LDS>
+// SINGLE: one instance of the batch has runs, so its constants are uniform across the workgroup
+// (the compiler keeps them in scalar registers) and queue ids are its trajectory ids.
+template <int POT, int BIAS, bool LDS, bool SINGLE = false>
 __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
     unsigned char *lds = fpt_lds;
     unsigned char *gslice = a.slices + static_cast<size_t>(blockIdx.x) * a.lay.slice_bytes;
@@ -166,6 +168,21 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
     MlpTiles tiles;
     if constexpr (BIAS == BIAS_MLP) mlp_load_tiles(a.mlp_params, tiles);
     MlpConsts mc{};
+    int single_inst = 0;
+    if constexpr (SINGLE) {
+        // the one instance with runs (others in the batch, if any, have none)
+        single_inst = static_cast<int>(a.order[0]);
+        const InstDev &I = a.inst[single_inst];
+        C = I.c;
+        stream = I.stream;
+        n_bins = I.n_bins;
+        row_base = I.row_base;
+        thr_base = I.thr_base;
+        dump_slot = I.dump_slot;
+        k_center = I.k_center;
+        if constexpr (BIAS == BIAS_MLP) mc = I.mlp;
+        cur_inst = single_inst;
+    }
 
     while (true) {
         // ---- refill: hand new trajectory ids to lanes that need one
@@ -192,14 +209,19 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
             if (need) {
                 need = false;
                 if (v < a.v_total) {
-                    int lo = 0, hi = a.n_inst;
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (a.vbeg_sorted[mid] <= v) lo = mid; else hi = mid;
+                    int ii = single_inst;
+                    if constexpr (SINGLE) {
+                        t = v;                 // the only instance with runs starts the queue
+                    } else {
+                        int lo = 0, hi = a.n_inst;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (a.vbeg_sorted[mid] <= v) lo = mid; else hi = mid;
+                        }
+                        ii = static_cast<int>(a.order[lo]);
+                        t = v - a.vbeg_sorted[lo];
                     }
-                    const int ii = static_cast<int>(a.order[lo]);
-                    t = v - a.vbeg_sorted[lo];
-                    if (ii != cur_inst) {
+                    if (!SINGLE && ii != cur_inst) {
                         const InstDev &I = a.inst[ii];
                         C = I.c;
                         stream = I.stream;
@@ -362,6 +384,13 @@ __global__ __launch_bounds__(1024) void fpt_step_kernel(StepArgs a) {
 template <int POT, bool LDS>
 __global__ __launch_bounds__(256) void fpt_step_mlp_kernel(StepArgs a) {
     fpt_step_body<POT, BIAS_MLP, LDS>(a);
+}
+
+// One instance: uniform constants in scalar registers, fitted to two waves per SIMD so that one
+// wave's matrix-core work overlaps another's vector work.
+template <int POT, bool LDS>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fpt_step_mlp1_kernel(StepArgs a) {
+    fpt_step_body<POT, BIAS_MLP, LDS, true>(a);
 }
 
 __global__ void fpt_init_queue_kernel(unsigned long long *q) {
@@ -587,7 +616,7 @@ static hipError_t launch_step_t(int n_wg, int block, size_t lds_bytes, const Ste
     void (*kern)(StepArgs);
     if constexpr (BIAS == BIAS_MLP) {
         if (block > 256) return hipErrorInvalidConfiguration;
-        kern = fpt_step_mlp_kernel<POT, LDS>;
+        kern = args.n_inst == 1 ? fpt_step_mlp1_kernel<POT, LDS> : fpt_step_mlp_kernel<POT, LDS>;
     } else {
         kern = fpt_step_kernel<POT, BIAS, LDS>;
     }

@@ -384,7 +384,9 @@ WsMap ws_map(const Prepared &P, int n_wg) {
 void resolve_cfg(const Device &d, const Prepared &P, LaunchCfg &c, bool &lds) {
     const bool mlp = P.bias == PYFPT_BIAS_MLP;
     if (c.block <= 0) c.block = mlp ? 256 : 512;
-    if (c.wg_per_cu <= 0) c.wg_per_cu = mlp ? 1 : 2;
+    // the learned bias with one active instance fits two waves per SIMD (two 256-thread
+    // workgroups per CU); otherwise one
+    if (c.wg_per_cu <= 0) c.wg_per_cu = mlp ? (P.order.size() == 1 ? 2 : 1) : 2;
     if (c.chunk <= 0) c.chunk = 1;
     // LDS budget per workgroup: the CU's LDS shared by its resident workgroups
     const size_t budget = std::min<size_t>(d.max_lds, 160 * 1024 / static_cast<size_t>(c.wg_per_cu));
@@ -1062,7 +1064,7 @@ int pyfpt_train_proposal(const pyfpt_instance *inst, uint64_t seed, const pyfpt_
         pyfpt_options so{};
         so.stream = stream;
         so.block = opt && opt->block ? opt->block : 256;
-        so.wg_per_cu = opt && opt->wg_per_cu ? opt->wg_per_cu : 1;
+        so.wg_per_cu = opt && opt->wg_per_cu ? opt->wg_per_cu : 2;
         so.chunk = opt && opt->chunk ? opt->chunk : 1;
         so.dump.n = ns;
         so.dump.stride = 1;

@@ -95,3 +95,50 @@ def test_build_flags_forbid_packed_fp32_and_contraction():
     f = " ".join(build.HIPCC_FLAGS)
     assert "-packed-fp32-ops" in f and "-ffp-contract=off" in f
     assert "-fhip-fp32-correctly-rounded-divide-sqrt" in f
+
+
+def test_training_and_combine_entry_points_reject_bad_input(lib):
+    """Validation happens before any device work, so these run without a GPU."""
+    import workloads as W
+    from paper_2206_11234_amd.api import make_instance
+    L = lib.load()
+    keep = [{}]
+    inst = make_instance(W.c2(10)[3], 16, keep)
+    opt = lib.pyfpt_options()
+    t = np.arange(2, dtype=np.uint64)
+    off = np.array([0, 3, 2], np.uint64)                       # not ascending
+    rec = np.zeros(3, np.dtype([("a", "<u4")] * 0 + [("phi", "<f4"), ("k", "<u4"), ("H", "<f4"), ("pn", "<u4")]))
+    k = np.zeros(2, np.uint32)
+    lw = np.zeros(2)
+    st = np.zeros(2, np.int32)
+    vp = lambda a: ctypes.c_void_p(a.ctypes.data)
+    assert L.pyfpt_proposal_records(ctypes.byref(inst), 0, vp(t), 2, 3, vp(off), vp(rec), vp(k), vp(lw), vp(st),
+                                    ctypes.byref(opt)) == lib.PYFPT_EINVAL          # group 3
+    assert L.pyfpt_proposal_records(ctypes.byref(inst), 0, vp(t), 2, 4, vp(off), vp(rec), vp(k), vp(lw), vp(st),
+                                    ctypes.byref(opt)) == lib.PYFPT_EINVAL          # offsets
+    net = lib.pyfpt_mlp()
+    net.hidden = 64
+    theta = np.zeros(4481, np.float32)
+    loss = np.zeros(1)
+    grad = np.zeros(4481)
+    lwt = np.zeros(2)
+    off2 = np.array([0, 1, 3], np.uint64)
+    rec["pn"] = [(0 << 3) | 4, (1 << 3) | 4, (5 << 3) | 4]       # path index 5 >= n_paths
+    assert L.pyfpt_proposal_loss_grad(ctypes.byref(net), 196.0, 1e-3, vp(theta), vp(rec), 3, vp(off2), 2, vp(lw), 10.0,
+                                      0, vp(loss), vp(grad), vp(lwt), ctypes.byref(opt)) == lib.PYFPT_EINVAL
+    rec["pn"] = [(0 << 3) | 4, (1 << 3) | 0, (1 << 3) | 4]       # zero steps in a group
+    assert L.pyfpt_proposal_loss_grad(ctypes.byref(net), 196.0, 1e-3, vp(theta), vp(rec), 3, vp(off2), 2, vp(lw), 10.0,
+                                      0, vp(loss), vp(grad), vp(lwt), ctypes.byref(opt)) == lib.PYFPT_EINVAL
+    rec["pn"] = [(0 << 3) | 4, (1 << 3) | 4, (1 << 3) | 4]
+    assert L.pyfpt_proposal_loss_grad(ctypes.byref(net), 196.0, 1e-3, vp(theta), vp(rec), 3, vp(off2), 2, vp(lw), 10.0,
+                                      2, vp(loss), vp(grad), vp(lwt), ctypes.byref(opt)) == lib.PYFPT_EINVAL  # objective
+    cfg = lib.pyfpt_train_config(10.0, 5.0, 100, 0, 1, 1, 4, 1e-3, 0.9, 0.999, 1e-8, 0, 0)   # lo > hi
+    inst.bias.kind = lib.BIAS_MLP
+    bf = np.zeros(4481, np.uint16)
+    rep = (lib.pyfpt_train_report * 1)()
+    assert L.pyfpt_train_proposal(ctypes.byref(inst), 0, ctypes.byref(cfg), vp(theta), vp(bf),
+                                  ctypes.cast(rep, ctypes.c_void_p), ctypes.byref(opt)) == lib.PYFPT_EINVAL
+    res = (lib.pyfpt_result * 1)()
+    lp = np.zeros(4)
+    assert L.pyfpt_combine(res, 1, 4, 16, 3, vp(lp), vp(lp), vp(lp)) == lib.PYFPT_EINVAL          # estimator 3
+    assert L.pyfpt_combine(res, 0, 4, 16, 0, vp(lp), vp(lp), vp(lp)) == lib.PYFPT_EINVAL          # no results

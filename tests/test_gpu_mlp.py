@@ -80,3 +80,24 @@ def test_constant_network_sampler_bit_exact(fpt, every):
     res, dump, _ = fpt.run(inst, 0, block=256, wg_per_cu=1, chunk=1, dump_n=inst.n_traj)
     tr = O.simulate(to_model(base), 0, base.n_traj)
     assert_dump_matches(dump, tr)
+
+
+def test_learned_bias_batches_match_single_runs(fpt):
+    """Two learned-bias instances sharing a network in one batch (the general kernel) give each
+    instance's runs exactly as a launch of that instance alone (the single-instance kernel), and
+    a batch whose first instance has no runs takes the single-instance kernel for the other."""
+    import dataclasses
+    params = W.c4_params(3, out_scale=1.0)
+    a = W.c4_instance(params, n_traj=700, stream=3)
+    b = dataclasses.replace(W.c4_instance(params, n_traj=500, stream=4), target_N=150.0)
+    _, dumps, _ = fpt.run_batch([a, b], 0, block=256, wg_per_cu=1, chunk=1, dump_n=700)
+    for inst, d in zip((a, b), dumps):
+        _, d1, _ = fpt.run(inst, 0, block=256, wg_per_cu=2, chunk=1, dump_n=700)
+        n = inst.n_traj
+        assert np.array_equal(d.k[:n], d1.k[:n]) and np.array_equal(d.lw[:n], d1.lw[:n])
+        assert np.array_equal(d.status[:n], d1.status[:n])
+    empty = dataclasses.replace(a, n_traj=0)
+    res, dumps, _ = fpt.run_batch([empty, b], 0, block=256, wg_per_cu=2, chunk=1, dump_n=700)
+    _, d1, _ = fpt.run(b, 0, block=256, wg_per_cu=2, chunk=1, dump_n=700)
+    assert np.array_equal(dumps[1].k[:500], d1.k[:500]) and np.array_equal(dumps[1].lw[:500], d1.lw[:500])
+    assert res[0].n_traj == 0 and int(res[0].count.sum()) == 0 and int(res[1].count.sum()) == 500
