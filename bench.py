@@ -56,13 +56,16 @@ def parse():
     p.add_argument("--learned", action="store_true",
                    help="learned proposal vs the fixed-bias scan at equal error in the far-tail window")
     p.add_argument("--n-eval", type=int, default=1_000_000)
-    p.add_argument("--n-sample", type=int, default=100_000)
+    p.add_argument("--n-sample", type=int, default=200_000)
     p.add_argument("--rounds", type=int, default=3)
     p.add_argument("--train-steps", type=int, default=40)
-    p.add_argument("--max-paths", type=int, default=2000)
+    p.add_argument("--max-paths", type=int, default=8000)
     p.add_argument("--lr", type=float, default=3e-3)
     p.add_argument("--target", type=float, default=196.0)
     p.add_argument("--objective", type=int, default=1, help="0: log M2, 1: cross entropy")
+    p.add_argument("--temper", type=float, default=0.5, help="w_0^temper in the path weights")
+    p.add_argument("--train-seed", type=int, default=1)
+    p.add_argument("--stride", type=int, default=1, help="record stride of the training sums")
     p.add_argument("--curriculum", type=str, default="60,100,140",
                    help="comma-separated window centres trained in turn before the target")
     p.add_argument("--c5", action="store_true",
@@ -166,8 +169,8 @@ def learned_gain(args):
     """GPU-seconds to a 1% median relative error over the far-tail window, learned proposal vs
     the fixed noise-scaled bias scan, on the diffusion-dominated quadratic case (m = 1,
     phi_in = 6, wall at 8, dN = 1e-3).  The learned network starts at r = 1 (small random
-    weights) and is trained on runs of its own proposal (seeds 1 + round); both are evaluated
-    on seed 2."""
+    weights) and is trained with the tempered cross-entropy objective through a curriculum of
+    windows, on runs of its own proposal; both are evaluated on seed 2."""
     import dataclasses
     import numpy as np
     import torch
@@ -212,9 +215,11 @@ def learned_gain(args):
     rep = []
     for si, centre in enumerate(stages):
         st_inst = dataclasses.replace(inst0, target_N=centre)
-        theta, bf, r_stage = F.train_proposal(st_inst, 1 + 100 * si, theta, window=(centre - 6.0, centre + 6.0),
-                                              n_sample=args.n_sample, rounds=args.rounds, steps=args.train_steps,
-                                              max_paths=args.max_paths, lr=args.lr, objective=args.objective)
+        theta, bf, r_stage = F.train_proposal(st_inst, args.train_seed + 100 * si, theta,
+                                              window=(centre - 6.0, centre + 6.0), n_sample=args.n_sample,
+                                              rounds=args.rounds, steps=args.train_steps, max_paths=args.max_paths,
+                                              lr=args.lr, objective=args.objective, temper=args.temper,
+                                              stride=args.stride if args.objective == 1 else 1)
         for r in r_stage:
             r["centre"] = centre
             print(f"[learned] train round: {json.dumps(r)}", file=sys.stderr, flush=True)

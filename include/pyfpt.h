@@ -296,21 +296,27 @@ typedef struct pyfpt_record {
 /*
  * Replay the runs t_ids[0..n_paths) of a sampling run (same instance, same seed) under the
  * instance's proposal, with the sampler's own arithmetic, and cut them into records: path i
- * writes rec[rec_off[i] .. rec_off[i+1]), which must be its ceil(k_i / group) records.  All
+ * writes rec[rec_off[i] .. rec_off[i+1]), which must be its records: with stride s >= 1 only the
+ * groups g = 0, s, 2s, ... are kept, ceil(ceil(k_i / group) / s) records.  All
  * arrays are host memory; k_out, lw_out and status_out receive the replayed run (identical to
  * the sampled one), so a caller can check the slots.  EINVAL: group not 1 or 4, rec_off not
- * ascending, or the instance as in pyfpt_run.  The call synchronises.
+ * ascending, stride < 1, or the instance as in pyfpt_run.  The call synchronises.
  */
 int pyfpt_proposal_records(const pyfpt_instance *inst, uint64_t seed, const uint64_t *t_ids, int32_t n_paths,
-                           int32_t group, const uint64_t *rec_off, pyfpt_record *rec, uint32_t *k_out,
-                           double *lw_out, int32_t *status_out, const pyfpt_options *opt);
+                           int32_t group, int32_t stride, const uint64_t *rec_off, pyfpt_record *rec,
+                           uint32_t *k_out, double *lw_out, int32_t *status_out, const pyfpt_options *opt);
 
 /*
  * The objective and its gradient from records (host arrays).  objective 0: log M2(theta) as
  * above; objective 1: the cross entropy sum_i c_i ln w_theta,i with c_i = w_0,i / sum_j w_0,j,
  * i.e. the Kullback-Leibler divergence of the proposal from the target restricted to the
  * window, up to a theta-independent constant (its minimiser is the same zero-variance
- * proposal, and its path weights do not depend on theta).  theta holds the 4481 binary32
+ * proposal, and its path weights do not depend on theta).  temper = beta in (0, 1]: w_0 enters
+ * the path weights as w_0^beta (1 = the objectives as written; a smaller beta gives a gradient
+ * less dominated by the few heaviest runs while the proposal is poor; the estimates of any run
+ * stay unbiased whatever proposal results).  rec_weight = the record stride s: each record
+ * stands for s groups (1 for complete records; s > 1 only with objective 1, whose path
+ * weights do not depend on the sums being estimated).  theta holds the 4481 binary32
  * master parameters in the order of pyfpt_mlp; net supplies the input normalisation and
  * out_scale (its params are not read); dN as in the sampling run; lw0[i] = ln w_0 of path i;
  * n_total = number of runs drawn.  Outputs: *loss, grad[4481] (binary64), lw_theta[n_paths].
@@ -320,8 +326,9 @@ int pyfpt_proposal_records(const pyfpt_instance *inst, uint64_t seed, const uint
  */
 int pyfpt_proposal_loss_grad(const pyfpt_mlp *net, double target_N, double dN, const float *theta,
                              const pyfpt_record *rec, uint64_t n_rec, const uint64_t *rec_off, int32_t n_paths,
-                             const double *lw0, double n_total, int32_t objective, double *loss, double *grad,
-                             double *lw_theta, const pyfpt_options *opt);
+                             const double *lw0, double n_total, int32_t objective, double temper,
+                             double rec_weight, double *loss, double *grad, double *lw_theta,
+                             const pyfpt_options *opt);
 
 typedef struct pyfpt_train_config {
     double window_lo, window_hi;     /* target window B* = (lo, hi] in N */
@@ -332,6 +339,8 @@ typedef struct pyfpt_train_config {
     int32_t group;                   /* 1 or 4: the network's evaluation interval */
     float lr, beta1, beta2, eps;     /* Adam */
     int32_t objective;               /* 0: log M2; 1: cross entropy (see pyfpt_proposal_loss_grad) */
+    float temper;                    /* beta in (0, 1] of pyfpt_proposal_loss_grad */
+    int32_t stride;                  /* record stride (>= 1; > 1 needs objective 1) */
     int32_t reserved;
 } pyfpt_train_config;
 

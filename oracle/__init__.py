@@ -96,11 +96,12 @@ def lib():
         L.oracle_simulate.restype = ctypes.c_int
         L.oracle_mlp_r_batch.argtypes = [ctypes.POINTER(_Params), f32p, f32p, f64p, ctypes.c_int64]
         vp = ctypes.c_void_p
-        L.oracle_records.argtypes = [ctypes.POINTER(_Params), u64p, ctypes.c_int64, ctypes.c_int, u64p, vp,
-                                     u64p, f64p, i32p]
+        L.oracle_records.argtypes = [ctypes.POINTER(_Params), u64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, u64p,
+                                     vp, u64p, f64p, i32p]
         L.oracle_records.restype = ctypes.c_int64
         L.oracle_loss_grad.argtypes = [ctypes.POINTER(_Params), f64p, vp, u64p, ctypes.c_int64, f64p,
-                                       ctypes.c_double, ctypes.c_int, f64p, f64p, f64p, f64p]
+                                       ctypes.c_double, ctypes.c_int, ctypes.c_double, ctypes.c_double, f64p, f64p,
+                                       f64p, f64p]
         _lib = L
     return _lib
 
@@ -217,9 +218,9 @@ class Records:
     status: np.ndarray
 
 
-def records(model: Model, seed: int, t_ids, E: int) -> Records:
+def records(model: Model, seed: int, t_ids, E: int, stride: int = 1) -> Records:
     """Replay the paths t_ids under the model's proposal (binary32 mirror) and cut each into
-    records at multiples of E steps."""
+    records at multiples of E steps, keeping the groups g = 0, stride, 2 stride, ..."""
     L = lib()
     t = np.ascontiguousarray(t_ids, np.uint64)
     n = t.size
@@ -228,20 +229,23 @@ def records(model: Model, seed: int, t_ids, E: int) -> Records:
     lw = np.zeros(n, np.float64)
     st = np.zeros(n, np.int32)
     off = np.zeros(n + 1, np.uint64)
-    L.oracle_records(ctypes.byref(P), _ptr(t, ctypes.c_uint64), n, int(E), _ptr(off, ctypes.c_uint64), None,
-                     _ptr(k, ctypes.c_uint64), _ptr(lw, ctypes.c_double), _ptr(st, ctypes.c_int32))
-    off[1:] = np.cumsum((k + np.uint64(E - 1)) // np.uint64(E))
+    L.oracle_records(ctypes.byref(P), _ptr(t, ctypes.c_uint64), n, int(E), int(stride), _ptr(off, ctypes.c_uint64),
+                     None, _ptr(k, ctypes.c_uint64), _ptr(lw, ctypes.c_double), _ptr(st, ctypes.c_int32))
+    groups = (k + np.uint64(E - 1)) // np.uint64(E)
+    off[1:] = np.cumsum((groups + np.uint64(stride - 1)) // np.uint64(stride))
     rec = np.zeros(int(off[-1]), RECORD_DTYPE)
-    bad = L.oracle_records(ctypes.byref(P), _ptr(t, ctypes.c_uint64), n, int(E), _ptr(off, ctypes.c_uint64),
+    bad = L.oracle_records(ctypes.byref(P), _ptr(t, ctypes.c_uint64), n, int(E), int(stride), _ptr(off, ctypes.c_uint64),
                            ctypes.c_void_p(rec.ctypes.data), _ptr(k, ctypes.c_uint64), _ptr(lw, ctypes.c_double),
                            _ptr(st, ctypes.c_int32))
     assert bad == 0
     return Records(rec, off, k, lw, st)
 
 
-def loss_grad(model: Model, theta, recs: Records, lw0, n_total: float, objective: int = 0):
+def loss_grad(model: Model, theta, recs: Records, lw0, n_total: float, objective: int = 0, temper: float = 1.0,
+              rec_weight: float = 1.0):
     """Objective 0: log M2(theta); objective 1: the cross entropy sum_i c_i ln w_theta,i with
-    c_i proportional to w_0,i.  Returns the loss, its gradient (4481) and ln w_theta per path.
+    c_i proportional to w_0,i; temper = beta uses w_0^beta in the path weights.  Returns the
+    loss, its gradient (4481) and ln w_theta per path.
     model supplies the input normalisation, out_scale, N* and dN."""
     L = lib()
     th = np.ascontiguousarray(theta, np.float64)
@@ -255,7 +259,7 @@ def loss_grad(model: Model, theta, recs: Records, lw0, n_total: float, objective
     scratch = np.zeros(max(n, 1) * 4481)
     L.oracle_loss_grad(ctypes.byref(P), _ptr(th, ctypes.c_double), ctypes.c_void_p(recs.rec.ctypes.data),
                        _ptr(recs.off, ctypes.c_uint64), n, _ptr(lw0, ctypes.c_double), float(n_total),
-                       int(objective), _ptr(loss, ctypes.c_double), _ptr(grad, ctypes.c_double), _ptr(lwt, ctypes.c_double),
+                       int(objective), float(temper), float(rec_weight), _ptr(loss, ctypes.c_double), _ptr(grad, ctypes.c_double), _ptr(lwt, ctypes.c_double),
                        _ptr(scratch, ctypes.c_double))
     return float(loss[0]), grad, lwt
 

@@ -627,7 +627,7 @@ typedef struct {
 
 /* Replay one path under the model's own proposal (binary32 mirror, identical to simulate_f32)
  * and cut it into records at multiples of E steps; at most cap records are written. */
-static int64_t records_f32(const oracle_params *P, const consts_f32 *c, uint64_t t, uint32_t path, int E,
+static int64_t records_f32(const oracle_params *P, const consts_f32 *c, uint64_t t, uint32_t path, int E, int stride,
                            oracle_record *rec, int64_t cap, uint64_t *k_out, double *lw_out, int *st_out)
 {
     float phi = c->phi_in;
@@ -675,13 +675,16 @@ static int64_t records_f32(const oracle_params *P, const consts_f32 *c, uint64_t
         else if (k >= P->k_max) status = ST_CENSORED;
         else if (phi > c->phi_esc) status = ST_ESCAPED;
         if (k % (uint64_t)E == 0 || status != ST_RUNNING) {
-            if (n_rec < cap) {
-                rec[n_rec].phi = phi_e;
-                rec[n_rec].k = k_e;
-                rec[n_rec].H = H;
-                rec[n_rec].pn = (path << 3) | n_e;
+            /* keep the groups g = 0, stride, 2 stride, ... */
+            if ((k_e / (uint32_t)E) % (uint32_t)stride == 0) {
+                if (n_rec < cap) {
+                    rec[n_rec].phi = phi_e;
+                    rec[n_rec].k = k_e;
+                    rec[n_rec].H = H;
+                    rec[n_rec].pn = (path << 3) | n_e;
+                }
+                n_rec += 1;
             }
-            n_rec += 1;
         }
     }
     *k_out = k;
@@ -690,11 +693,12 @@ static int64_t records_f32(const oracle_params *P, const consts_f32 *c, uint64_t
     return n_rec;
 }
 
-/* Records of the paths t_ids[0..n): path i owns rec[rec_off[i] .. rec_off[i+1]).  Returns the
+/* Records of the paths t_ids[0..n): path i owns rec[rec_off[i] .. rec_off[i+1]); with stride s only
+ * the groups g = 0, s, 2s, ... are kept, each record then standing for s groups.  Returns the
  * number of paths whose record count did not match their slot (0 when the offsets came from
  * the same paths' step counts). */
-int64_t oracle_records(const oracle_params *P, const uint64_t *t_ids, int64_t n, int E, const uint64_t *rec_off,
-                       oracle_record *rec, uint64_t *k_out, double *lw_out, int32_t *st_out)
+int64_t oracle_records(const oracle_params *P, const uint64_t *t_ids, int64_t n, int E, int stride,
+                       const uint64_t *rec_off, oracle_record *rec, uint64_t *k_out, double *lw_out, int32_t *st_out)
 {
     consts_f32 c;
     make_consts_f32(P, &c);
@@ -705,7 +709,7 @@ int64_t oracle_records(const oracle_params *P, const uint64_t *t_ids, int64_t n,
     for (int64_t i = 0; i < n; ++i) {
         int st;
         const int64_t cap = (int64_t)(rec_off[i + 1] - rec_off[i]);
-        const int64_t got = records_f32(P, &c, t_ids[i], (uint32_t)i, E, rec + rec_off[i], cap, &k_out[i],
+        const int64_t got = records_f32(P, &c, t_ids[i], (uint32_t)i, E, stride, rec + rec_off[i], cap, &k_out[i],
                                         &lw_out[i], &st);
         st_out[i] = st;
         if (got != cap) bad += 1;
@@ -746,11 +750,15 @@ static double net_f64(const oracle_params *P, const double *th, float phi, uint3
  *       c_i = w_0,i / sum_j w_0,j (the weights do not depend on theta),
  *       dL/dtheta = sum_i c_i d ln w_theta,i / dtheta.
  * In both, d ln w_theta / dtheta = sum_e (r_e n_e dN - H_e) d r_e / dtheta.
+ * temper = beta in (0, 1] replaces w_0 by w_0^beta in the path weights c_i (beta = 1: the
+ * objectives as written; smaller beta trades the bias of a tempered target for a gradient less
+ * dominated by the few heaviest runs while the proposal is still poor).  rec_weight: each record
+ * stands for that many groups (records kept at a stride: unbiased estimates of the path sums).
  * grad_path (n_paths x 4481 scratch) keeps the per-path sums so the total is summed in path
  * order. */
 void oracle_loss_grad(const oracle_params *P, const double *theta, const oracle_record *rec, const uint64_t *rec_off,
-                      int64_t n_paths, const double *lw0, double n_total, int objective, double *loss, double *grad,
-                      double *lw_theta, double *grad_path)
+                      int64_t n_paths, const double *lw0, double n_total, int objective, double temper,
+                      double rec_weight, double *loss, double *grad, double *lw_theta, double *grad_path)
 {
     const float dN_f = (float)P->dN;
     const double dN = (double)dN_f;
@@ -762,20 +770,20 @@ void oracle_loss_grad(const oracle_params *P, const double *theta, const oracle_
         for (uint64_t e = rec_off[i]; e < rec_off[i + 1]; ++e) {
             const double r = net_f64(P, theta, rec[e].phi, rec[e].k, dN_f, x, h1, h2);
             const double n = (double)(rec[e].pn & 7u);
-            s += -r * (double)rec[e].H + r * r * n * dN * 0.5;
+            s += (-r * (double)rec[e].H + r * r * n * dN * 0.5) * rec_weight;
         }
         lw_theta[i] = s;
     }
     const double use_t = objective == 0 ? 1.0 : 0.0;
     double M = -INFINITY;
-    for (int64_t i = 0; i < n_paths; ++i) M = fmax(M, lw0[i] + use_t * lw_theta[i]);
+    for (int64_t i = 0; i < n_paths; ++i) M = fmax(M, temper * lw0[i] + use_t * lw_theta[i]);
     double S = 0.0;
-    for (int64_t i = 0; i < n_paths; ++i) S += exp(lw0[i] + use_t * lw_theta[i] - M);
+    for (int64_t i = 0; i < n_paths; ++i) S += exp(temper * lw0[i] + use_t * lw_theta[i] - M);
     if (objective == 0) {
         *loss = M + log(S) - log(n_total);
     } else {
         double L = 0.0;
-        for (int64_t i = 0; i < n_paths; ++i) L += exp(lw0[i] - M) / S * lw_theta[i];
+        for (int64_t i = 0; i < n_paths; ++i) L += exp(temper * lw0[i] - M) / S * lw_theta[i];
         *loss = L;
     }
     const double *W2 = theta + 256, *w3 = theta + 4416;
@@ -786,12 +794,12 @@ void oracle_loss_grad(const oracle_params *P, const double *theta, const oracle_
     for (int64_t i = 0; i < n_paths; ++i) {
         double *g = grad_path + (size_t)i * 4481;
         for (int j = 0; j < 4481; ++j) g[j] = 0.0;
-        const double ci = exp(lw0[i] + use_t * lw_theta[i] - M) / S;
+        const double ci = exp(temper * lw0[i] + use_t * lw_theta[i] - M) / S;
         double x[3], h1[64], h2[64], d2[64];
         for (uint64_t e = rec_off[i]; e < rec_off[i + 1]; ++e) {
             const double r = net_f64(P, theta, rec[e].phi, rec[e].k, dN_f, x, h1, h2);
             const double n = (double)(rec[e].pn & 7u);
-            const double go = ci * (r * n * dN - (double)rec[e].H) * osc;   /* d loss / d o, o = w3.h2 + b3 */
+            const double go = ci * (r * n * dN - (double)rec[e].H) * osc * rec_weight;   /* d loss / d o */
             g[4480] += go;
             for (int u = 0; u < 64; ++u) {
                 g[4416 + u] += go * h2[u];

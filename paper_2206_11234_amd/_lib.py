@@ -82,7 +82,7 @@ class pyfpt_train_config(ctypes.Structure):
                 ("max_paths", ctypes.c_int32), ("rounds", ctypes.c_int32), ("steps", ctypes.c_int32),
                 ("group", ctypes.c_int32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
                 ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("objective", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("temper", ctypes.c_float), ("stride", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class pyfpt_train_report(ctypes.Structure):
@@ -127,11 +127,11 @@ def load() -> ctypes.CDLL:
     vp = ctypes.c_void_p
     L.pyfpt_combine.argtypes = [P(pyfpt_result), ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                 vp, vp, vp]
-    L.pyfpt_proposal_records.argtypes = [P(pyfpt_instance), ctypes.c_uint64, vp, ctypes.c_int32, ctypes.c_int32, vp, vp,
-                                         vp, vp, vp, P(pyfpt_options)]
+    L.pyfpt_proposal_records.argtypes = [P(pyfpt_instance), ctypes.c_uint64, vp, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.c_int32, vp, vp, vp, vp, vp, P(pyfpt_options)]
     L.pyfpt_proposal_loss_grad.argtypes = [P(pyfpt_mlp), ctypes.c_double, ctypes.c_double, vp, vp, ctypes.c_uint64, vp,
-                                           ctypes.c_int32, vp, ctypes.c_double, ctypes.c_int32, vp, vp, vp,
-                                           P(pyfpt_options)]
+                                           ctypes.c_int32, vp, ctypes.c_double, ctypes.c_int32, ctypes.c_double,
+                                           ctypes.c_double, vp, vp, vp, P(pyfpt_options)]
     L.pyfpt_train_proposal.argtypes = [P(pyfpt_instance), ctypes.c_uint64, P(pyfpt_train_config), vp, vp, vp,
                                        P(pyfpt_options)]
     L.pyfpt_last_error.restype = ctypes.c_char_p

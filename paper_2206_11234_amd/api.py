@@ -365,29 +365,31 @@ def _ptr(a):
     return ctypes.c_void_p(a.ctypes.data)
 
 
-def proposal_records(inst, seed: int, t_ids, k, group: int) -> Records:
+def proposal_records(inst, seed: int, t_ids, k, group: int, stride: int = 1) -> Records:
     """Replay the runs t_ids (whose step counts k are known from a dump) under the instance's
-    proposal and cut them into records (pyfpt_proposal_records)."""
+    proposal and cut them into records, every stride-th group (pyfpt_proposal_records)."""
     _torch()
     keep: list = [{}]
     I = make_instance(inst, 16, keep)
     t = np.ascontiguousarray(t_ids, np.uint64)
     k = np.asarray(k, np.uint64)
     off = np.zeros(t.size + 1, np.uint64)
-    off[1:] = np.cumsum((k + np.uint64(group - 1)) // np.uint64(group))
+    groups = (k + np.uint64(group - 1)) // np.uint64(group)
+    off[1:] = np.cumsum((groups + np.uint64(stride - 1)) // np.uint64(stride))
     rec = np.zeros(int(off[-1]), RECORD_DTYPE)
     k_out = np.zeros(t.size, np.uint32)
     lw_out = np.zeros(t.size, np.float64)
     st_out = np.zeros(t.size, np.int32)
     opt = L.pyfpt_options()
     opt.stream = ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
-    L.check(L.load().pyfpt_proposal_records(ctypes.byref(I), int(seed), _ptr(t), t.size, int(group), _ptr(off),
+    L.check(L.load().pyfpt_proposal_records(ctypes.byref(I), int(seed), _ptr(t), t.size, int(group), int(stride),
+                                            _ptr(off),
                                             _ptr(rec), _ptr(k_out), _ptr(lw_out), _ptr(st_out), ctypes.byref(opt)))
     return Records(rec, off, k_out.astype(np.uint64), lw_out, st_out)
 
 
 def proposal_loss_grad(params, target_N: float, dN: float, theta, recs: Records, lw0, n_total: float,
-                       objective: int = 0):
+                       objective: int = 0, temper: float = 1.0, rec_weight: float = 1.0):
     """The objective (0: log M2, 1: cross entropy), its gradient (4481, binary64) and ln w_theta
     per path, from records."""
     _torch()
@@ -406,13 +408,14 @@ def proposal_loss_grad(params, target_N: float, dN: float, theta, recs: Records,
     opt.stream = ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
     L.check(L.load().pyfpt_proposal_loss_grad(ctypes.byref(m), float(target_N), float(dN), _ptr(th), _ptr(rec),
                                               rec.size, _ptr(off), n, _ptr(lw0), float(n_total), int(objective),
-                                              _ptr(loss),
+                                              float(temper), float(rec_weight), _ptr(loss),
                                               _ptr(grad), _ptr(lwt), ctypes.byref(opt)))
     return float(loss[0]), grad, lwt
 
 
 def train_proposal(inst, seed: int, theta, *, window, n_sample: int, rounds: int, steps: int, max_paths: int = 0,
-                   lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, objective: int = 0):
+                   lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, objective: int = 0,
+                   temper: float = 1.0, stride: int = 1):
     """Train the learned proposal of `inst` (pyfpt_train_proposal).  Returns (theta, bf16 bits,
     list of per-round report dicts)."""
     _torch()
@@ -422,7 +425,7 @@ def train_proposal(inst, seed: int, theta, *, window, n_sample: int, rounds: int
     bf = np.zeros(4481, np.uint16)
     cfg = L.pyfpt_train_config(float(window[0]), float(window[1]), int(n_sample), int(max_paths), int(rounds),
                                int(steps), int(inst.mlp.eval_every), float(lr), float(beta1), float(beta2), float(eps),
-                               int(objective), 0)
+                               int(objective), float(temper), int(stride), 0)
     rep = (L.pyfpt_train_report * rounds)()
     opt = L.pyfpt_options()
     opt.stream = ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)

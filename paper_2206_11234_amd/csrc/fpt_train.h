@@ -27,6 +27,7 @@ struct RecordArgs {
     uint32_t n_paths;
     uint32_t key0, key1;        // Philox key = seed of the sampling run
     int32_t group;              // records per group of 1 or 4 steps
+    int32_t stride;             // keep the record of every stride-th group (g % stride == 0)
     int32_t mlp_every;
     const uint16_t *mlp_params; // bfloat16 network of the sampling proposal
     const uint64_t *rec_off;    // n_paths + 1 record offsets
@@ -44,11 +45,11 @@ struct TrainArgs {
     int32_t n_paths;
     int32_t n_part;             // workgroups of the backward pass
     int32_t objective;          // 0: log M2 (c ~ w_0 w_theta); 1: cross entropy (c ~ w_0)
-    int32_t pad0;
+    float temper;               // w_0 enters the path weights as w_0^temper
+    float rec_weight;           // each record stands for this many groups (the record stride)
     const float *theta;         // binary32 master parameters
     MlpConsts mc;               // input normalisation, output scale, N*
     float dN;                   // binary32 dN
-    float *r_buf;               // r per record
     double *lw_theta;           // ln w_theta per path
     const double *lw0;          // ln w_0 per path (sampled)
     double n_total;             // runs drawn

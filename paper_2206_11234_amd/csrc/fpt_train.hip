@@ -10,14 +10,18 @@
 // group e, n_e its length.  So a path reduces to records (phi_e, k_e, H_e, n_e):
 //
 //   fpt_record_kernel    replays paths under theta_0 (the sampler's own step and network code,
-//                        so the replay reproduces the sampled runs) and writes their records;
+//                        so the replay reproduces the sampled runs) and writes their records
+//                        (every group's, or every stride-th group's, each then standing for
+//                        stride groups: an unbiased estimate of the sums over a path);
 //   fpt_train_fwd_kernel r_theta per record (binary32 network on the master weights), per-path
 //                        sum of ln w_theta in binary64 (one workgroup per path, fixed order);
 //   fpt_train_softmax_kernel  c_i = w_0,i w_theta,i / sum_j w_0,j w_theta,j and log M2, or for
 //                        the cross-entropy objective c_i = w_0,i / sum_j w_0,j and
 //                        sum_i c_i ln w_theta,i (the KL divergence of the proposal from the
-//                        target restricted to the window, up to a constant);
-//   fpt_train_bwd_kernel gradient of log M2: per record the coefficient
+//                        target restricted to the window, up to a constant); w_0 may be
+//                        tempered to w_0^beta;
+//   fpt_train_bwd_kernel gradient of the objective: per record (forward recomputed in place) the
+//                        coefficient
 //                        c_i (r n dN - H) out_scale multiplies d(w3.h2 + b3)/d theta; each lane
 //                        back-propagates one record, and the weight gradient of the 64x64 layer,
 //                        a contraction over the 64 records of a wave, runs on
@@ -78,7 +82,8 @@ __global__ __launch_bounds__(256) void fpt_record_kernel(RecordArgs a) {
                 H = H + __builtin_fmaf(r, C.dN, sxi);
                 n_e += 1;
                 if ((k & emask) == 0 || st != ST_RUNNING) {
-                    if (n_rec < cap) {
+                    const uint32_t grp = k_e / static_cast<uint32_t>(a.group);
+                    if (grp % static_cast<uint32_t>(a.stride) == 0 && n_rec < cap) {
                         TrainRec R;
                         R.phi = phi_e;
                         R.k = k_e;
@@ -86,7 +91,7 @@ __global__ __launch_bounds__(256) void fpt_record_kernel(RecordArgs a) {
                         R.pn = (i << 3) | n_e;
                         a.rec[base + n_rec] = R;
                     }
-                    n_rec += 1;
+                    if (grp % static_cast<uint32_t>(a.stride) == 0) n_rec += 1;
                 }
             }
         }
@@ -157,10 +162,9 @@ __global__ __launch_bounds__(256) void fpt_train_fwd_kernel(TrainArgs a, const f
 #pragma unroll 1
         for (int u = 0; u < 64; ++u) o = __builtin_fmaf(th[NET_W3 + u], net_unit2(th, u, h1), o);
         const float r = a.mc.out_scale * (o + th0[NET_B3]);
-        a.r_buf[e] = r;
         const double rd = static_cast<double>(r);
         const double n = static_cast<double>(R.pn & 7u);
-        s += -rd * static_cast<double>(R.H) + rd * rd * n * hdN;
+        s += (-rd * static_cast<double>(R.H) + rd * rd * n * hdN) * static_cast<double>(a.rec_weight);
     }
     red[threadIdx.x] = s;
     __syncthreads();
@@ -179,7 +183,8 @@ __global__ __launch_bounds__(1024) void fpt_train_softmax_kernel(TrainArgs a) {
     const int tid = threadIdx.x;
     const double use_t = a.objective == 0 ? 1.0 : 0.0;
     double m = -INFINITY;
-    for (int i = tid; i < a.n_paths; i += 1024) m = fmax(m, a.lw0[i] + use_t * a.lw_theta[i]);
+    const double beta = static_cast<double>(a.temper);
+    for (int i = tid; i < a.n_paths; i += 1024) m = fmax(m, beta * a.lw0[i] + use_t * a.lw_theta[i]);
     red[tid] = m;
     __syncthreads();
     for (int w = 512; w > 0; w >>= 1) {
@@ -189,7 +194,7 @@ __global__ __launch_bounds__(1024) void fpt_train_softmax_kernel(TrainArgs a) {
     const double M = red[0];
     __syncthreads();
     double s = 0.0;
-    for (int i = tid; i < a.n_paths; i += 1024) s += exp(a.lw0[i] + use_t * a.lw_theta[i] - M);
+    for (int i = tid; i < a.n_paths; i += 1024) s += exp(beta * a.lw0[i] + use_t * a.lw_theta[i] - M);
     red[tid] = s;
     __syncthreads();
     for (int w = 512; w > 0; w >>= 1) {
@@ -200,7 +205,7 @@ __global__ __launch_bounds__(1024) void fpt_train_softmax_kernel(TrainArgs a) {
     __syncthreads();
     double ce = 0.0;
     for (int i = tid; i < a.n_paths; i += 1024) {
-        const double c = exp(a.lw0[i] + use_t * a.lw_theta[i] - M) / S;
+        const double c = exp(beta * a.lw0[i] + use_t * a.lw_theta[i] - M) / S;
         a.c[i] = c;
         ce += c * a.lw_theta[i];
     }
@@ -221,9 +226,10 @@ constexpr int TS = 65;  // padded row stride of the [sample][unit] LDS tiles
 typedef float f32x16v __attribute__((ext_vector_type(16)));
 
 __global__ __launch_bounds__(64) void fpt_train_bwd_kernel(TrainArgs a, const float *__restrict__ th0) {
-    __shared__ float HA[64 * TS];   // h1   [sample][unit]
-    __shared__ float HB[64 * TS];   // h2, then delta1
-    __shared__ float HC[64 * TS];   // delta2
+    // two [sample][unit] tiles: HA holds h1, then delta1; HB holds h2, then delta2 (34 KB with the
+    // inputs and coefficients, so four single-wave workgroups share a CU, one per SIMD)
+    __shared__ float HA[64 * TS];
+    __shared__ float HB[64 * TS];
     __shared__ float XS[64 * 4];
     __shared__ float GS[64];
     const int lane = threadIdx.x;
@@ -242,76 +248,103 @@ __global__ __launch_bounds__(64) void fpt_train_bwd_kernel(TrainArgs a, const fl
         const uint64_t e = tile * 64 + lane;
         const bool valid = e < a.n_rec;
         TrainRec R{};
+        if (valid) R = a.rec[e];
+        else R.phi = a.mc.in_mean[0];
+        // forward: h1 into HA, h2 into HB, and r (the same operations as the forward kernel)
         float g = 0.0f;
-        if (valid) {
-            R = a.rec[e];
-            const uint32_t path = R.pn >> 3;
-            const double n = static_cast<double>(R.pn & 7u);
-            const double r = static_cast<double>(a.r_buf[e]);
-            g = static_cast<float>(a.c[path] * (r * n * dNd - static_cast<double>(R.H)) *
-                                   static_cast<double>(a.mc.out_scale));
-        } else {
-            R.phi = a.mc.in_mean[0];
-        }
-        // forward
-        float x[3], h1[64];
-        net_inputs(a.mc, R.phi, R.k, a.dN, x);
-        net_layer1(th, x, h1);
+        {
+            float x[3], h1[64];
+            net_inputs(a.mc, R.phi, R.k, a.dN, x);
+            net_layer1(th, x, h1);
 #pragma unroll
-        for (int u = 0; u < 64; ++u) HA[lane * TS + u] = h1[u];
+            for (int u = 0; u < 64; ++u) HA[lane * TS + u] = h1[u];
+            float o = 0.0f;
 #pragma unroll 1
-        for (int u = 0; u < 64; ++u) HB[lane * TS + u] = net_unit2(th, u, h1);
-        XS[lane * 4 + 0] = x[0];
-        XS[lane * 4 + 1] = x[1];
-        XS[lane * 4 + 2] = x[2];
-        XS[lane * 4 + 3] = 1.0f;
-        GS[lane] = g;
-        // delta2 = g w3 (1 - h2^2)
-#pragma unroll 4
-        for (int u = 0; u < 64; ++u) {
-            const float h = HB[lane * TS + u];
-            HC[lane * TS + u] = (g * th[NET_W3 + u]) * __builtin_fmaf(-h, h, 1.0f);
+            for (int u = 0; u < 64; ++u) {
+                const float h2 = net_unit2(th, u, h1);
+                HB[lane * TS + u] = h2;
+                o = __builtin_fmaf(th[NET_W3 + u], h2, o);
+            }
+            if (valid) {
+                const double r = static_cast<double>(a.mc.out_scale * (o + th[NET_B3]));
+                const uint32_t path = R.pn >> 3;
+                const double n = static_cast<double>(R.pn & 7u);
+                g = static_cast<float>(a.c[path] * (r * n * dNd - static_cast<double>(R.H)) *
+                                       static_cast<double>(a.mc.out_scale) * static_cast<double>(a.rec_weight));
+            }
+            XS[lane * 4 + 0] = x[0];
+            XS[lane * 4 + 1] = x[1];
+            XS[lane * 4 + 2] = x[2];
+            XS[lane * 4 + 3] = 1.0f;
+            GS[lane] = g;
         }
         __syncthreads();
-        // lane = unit: w3, b2, b3
+        // lane = unit: w3 and b3 from h2
         {
-            float sw3 = 0.0f, sb2 = 0.0f, sb3 = 0.0f;
+            float sw3 = 0.0f, sb3 = 0.0f;
 #pragma unroll 4
             for (int s = 0; s < 64; ++s) {
                 const float gs = GS[s];
                 sw3 = __builtin_fmaf(gs, HB[s * TS + lane], sw3);
-                sb2 += HC[s * TS + lane];
                 sb3 += gs;
             }
             g_w3 += sw3;
-            g_b2 += sb2;
             g_b3 += sb3;
         }
         __syncthreads();
-        // delta1 = (W2^T delta2) (1 - h1^2), rows of W2 against this lane's delta2, into HB
+        // delta2 = g w3 (1 - h2^2), in place over this lane's h2
+#pragma unroll 4
+        for (int u = 0; u < 64; ++u) {
+            const float h = HB[lane * TS + u];
+            HB[lane * TS + u] = (g * th[NET_W3 + u]) * __builtin_fmaf(-h, h, 1.0f);
+        }
+        __syncthreads();
+        // lane = unit: b2 from delta2
+        {
+            float sb2 = 0.0f;
+#pragma unroll 4
+            for (int s = 0; s < 64; ++s) sb2 += HB[s * TS + lane];
+            g_b2 += sb2;
+        }
+        // dW2[u][v] += sum_s delta2[s][u] h1[s][v]: M = u, N = v, K = the tile's samples
+        {
+            const int row = lane & 31, kh = lane >> 5;
+#pragma unroll 4
+            for (int ks = 0; ks < 32; ++ks) {
+                const int s = 2 * ks + kh;
+                const float a0 = HB[s * TS + row], a1 = HB[s * TS + 32 + row];
+                const float b0 = HA[s * TS + row], b1 = HA[s * TS + 32 + row];
+                acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
+                acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
+                acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
+                acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+        // delta1 = (W2^T delta2) (1 - h1^2): rows of W2 against this lane's delta2, over its h1
         {
             float t1[64];
 #pragma unroll
             for (int v = 0; v < 64; ++v) t1[v] = 0.0f;
 #pragma unroll 1
             for (int u = 0; u < 64; ++u) {
-                const float d = HC[lane * TS + u];
+                const float d = HB[lane * TS + u];
 #pragma unroll
                 for (int v = 0; v < 64; ++v) t1[v] = __builtin_fmaf(th[NET_W2 + 64 * u + v], d, t1[v]);
             }
 #pragma unroll
             for (int v = 0; v < 64; ++v) {
                 const float h = HA[lane * TS + v];
-                HB[lane * TS + v] = t1[v] * __builtin_fmaf(-h, h, 1.0f);
+                HA[lane * TS + v] = t1[v] * __builtin_fmaf(-h, h, 1.0f);
             }
         }
         __syncthreads();
-        // lane = unit: W1, b1
+        // lane = unit: W1, b1 from delta1
         {
             float sb1 = 0.0f, s0 = 0.0f, s1 = 0.0f, s2 = 0.0f;
 #pragma unroll 4
             for (int s = 0; s < 64; ++s) {
-                const float d = HB[s * TS + lane];
+                const float d = HA[s * TS + lane];
                 sb1 += d;
                 s0 = __builtin_fmaf(d, XS[s * 4 + 0], s0);
                 s1 = __builtin_fmaf(d, XS[s * 4 + 1], s1);
@@ -321,18 +354,6 @@ __global__ __launch_bounds__(64) void fpt_train_bwd_kernel(TrainArgs a, const fl
             g_w1[0] += s0;
             g_w1[1] += s1;
             g_w1[2] += s2;
-        }
-        // dW2[u][v] += sum_s delta2[s][u] h1[s][v]: M = u, N = v, K = the tile's samples
-        const int row = lane & 31, kh = lane >> 5;
-#pragma unroll 4
-        for (int ks = 0; ks < 32; ++ks) {
-            const int s = 2 * ks + kh;
-            const float a0 = HC[s * TS + row], a1 = HC[s * TS + 32 + row];
-            const float b0 = HA[s * TS + row], b1 = HA[s * TS + 32 + row];
-            acc[0][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f32_32x32x2f32(a1, b1, acc[1][1], 0, 0, 0);
         }
         __syncthreads();
     }

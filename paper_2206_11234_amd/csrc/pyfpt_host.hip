@@ -706,7 +706,7 @@ MlpConsts mlp_consts(const pyfpt_mlp &m, double target_N) {
 }
 
 // Replay on the device: buffers already on the device; outputs per path on the device.
-int records_device(const Prepared &P, uint64_t seed, int group, const uint64_t *d_t, uint32_t n_paths,
+int records_device(const Prepared &P, uint64_t seed, int group, int stride, const uint64_t *d_t, uint32_t n_paths,
                    const uint64_t *d_off, TrainRec *d_rec, uint32_t *d_k, double *d_lw, int32_t *d_st,
                    uint64_t *d_nrec, hipStream_t stream) {
     RecordArgs ra{};
@@ -716,6 +716,7 @@ int records_device(const Prepared &P, uint64_t seed, int group, const uint64_t *
     ra.key0 = static_cast<uint32_t>(seed);
     ra.key1 = static_cast<uint32_t>(seed >> 32);
     ra.group = group;
+    ra.stride = stride;
     ra.mlp_every = P.mlp_every;
     ra.mlp_params = P.mlp_params;
     ra.rec_off = d_off;
@@ -736,7 +737,7 @@ int backward_groups(uint64_t n_rec) {
         if (get_device(&d) == PYFPT_OK) cus = d->cus;
     }
     const uint64_t tiles = (n_rec + 63) / 64;
-    const uint64_t cap = static_cast<uint64_t>(cus > 0 ? cus : 1) * 3;
+    const uint64_t cap = static_cast<uint64_t>(cus > 0 ? cus : 1) * 4;   // four backward workgroups per CU
     return static_cast<int>(std::max<uint64_t>(1, std::min(tiles, cap)));
 }
 
@@ -916,11 +917,12 @@ int pyfpt_combine(const pyfpt_result *res, int32_t n_res, int32_t n_bins, int32_
 }
 
 int pyfpt_proposal_records(const pyfpt_instance *inst, uint64_t seed, const uint64_t *t_ids, int32_t n_paths,
-                           int32_t group, const uint64_t *rec_off, pyfpt_record *rec, uint32_t *k_out,
-                           double *lw_out, int32_t *status_out, const pyfpt_options *opt) {
+                           int32_t group, int32_t stride, const uint64_t *rec_off, pyfpt_record *rec,
+                           uint32_t *k_out, double *lw_out, int32_t *status_out, const pyfpt_options *opt) {
     if (!inst || n_paths < 0 || (n_paths > 0 && (!t_ids || !rec_off || !k_out || !lw_out || !status_out)))
         return fail(PYFPT_EINVAL, "NULL argument or n_paths < 0");
     if (group != 1 && group != 4) return fail(PYFPT_EINVAL, "group must be 1 or 4");
+    if (stride < 1) return fail(PYFPT_EINVAL, "stride must be >= 1");
     if (n_paths >= (1 << 29)) return fail(PYFPT_EINVAL, "n_paths must be < 2^29");
     Prepared P;
     int rc = prepare(inst, 1, P);
@@ -937,7 +939,7 @@ int pyfpt_proposal_records(const pyfpt_instance *inst, uint64_t seed, const uint
         return rc;
     HIP_TRY(hipMemcpyAsync(t.p, t_ids, 8ull * n_paths, hipMemcpyHostToDevice, stream), "upload ids");
     HIP_TRY(hipMemcpyAsync(off.p, rec_off, 8ull * (n_paths + 1), hipMemcpyHostToDevice, stream), "upload offsets");
-    if ((rc = records_device(P, seed, group, t.as<uint64_t>(), static_cast<uint32_t>(n_paths), off.as<uint64_t>(),
+    if ((rc = records_device(P, seed, group, stride, t.as<uint64_t>(), static_cast<uint32_t>(n_paths), off.as<uint64_t>(),
                              r.as<TrainRec>(), k.as<uint32_t>(), lw.as<double>(), st.as<int32_t>(), nr.as<uint64_t>(),
                              stream)))
         return rc;
@@ -951,12 +953,16 @@ int pyfpt_proposal_records(const pyfpt_instance *inst, uint64_t seed, const uint
 
 int pyfpt_proposal_loss_grad(const pyfpt_mlp *net, double target_N, double dN, const float *theta,
                              const pyfpt_record *rec, uint64_t n_rec, const uint64_t *rec_off, int32_t n_paths,
-                             const double *lw0, double n_total, int32_t objective, double *loss, double *grad,
-                             double *lw_theta, const pyfpt_options *opt) {
+                             const double *lw0, double n_total, int32_t objective, double temper,
+                             double rec_weight, double *loss, double *grad, double *lw_theta,
+                             const pyfpt_options *opt) {
     if (!net || !theta || !rec_off || !lw0 || !loss || !grad || !lw_theta || (n_rec > 0 && !rec))
         return fail(PYFPT_EINVAL, "NULL argument");
     if (n_paths < 1 || n_paths >= (1 << 29)) return fail(PYFPT_EINVAL, "n_paths must be 1 .. 2^29-1");
     if (objective != 0 && objective != 1) return fail(PYFPT_EINVAL, "objective must be 0 or 1");
+    if (!(temper > 0.0 && temper <= 1.0)) return fail(PYFPT_EINVAL, "temper must be in (0, 1]");
+    if (!(rec_weight >= 1.0) || !std::isfinite(rec_weight) || (objective == 0 && rec_weight != 1.0))
+        return fail(PYFPT_EINVAL, "rec_weight must be >= 1 (and 1 for objective 0)");
     if (!(dN > 0) || !std::isfinite(dN) || !(n_total > 0) || !std::isfinite(target_N))
         return fail(PYFPT_EINVAL, "need finite dN > 0, n_total > 0 and finite target_N");
     int rc = check_offsets(rec_off, n_paths, n_rec);
@@ -969,9 +975,9 @@ int pyfpt_proposal_loss_grad(const pyfpt_mlp *net, double target_N, double dN, c
     }
     hipStream_t stream = opt ? static_cast<hipStream_t>(opt->stream) : nullptr;
     const int n_part = backward_groups(n_rec);
-    DevBuf r, off, th, rb, lwt, l0, c, ls, part, g;
+    DevBuf r, off, th, lwt, l0, c, ls, part, g;
     if ((rc = r.alloc(16ull * n_rec)) || (rc = off.alloc(8ull * (n_paths + 1))) || (rc = th.alloc(4ull * NET_N_PARAMS)) ||
-        (rc = rb.alloc(4ull * n_rec)) || (rc = lwt.alloc(8ull * n_paths)) || (rc = l0.alloc(8ull * n_paths)) ||
+        (rc = lwt.alloc(8ull * n_paths)) || (rc = l0.alloc(8ull * n_paths)) ||
         (rc = c.alloc(8ull * n_paths)) || (rc = ls.alloc(8)) ||
         (rc = part.alloc(4ull * NET_N_PARAMS * static_cast<uint64_t>(n_part))) || (rc = g.alloc(8ull * NET_N_PARAMS)))
         return rc;
@@ -986,10 +992,11 @@ int pyfpt_proposal_loss_grad(const pyfpt_mlp *net, double target_N, double dN, c
     ta.n_paths = n_paths;
     ta.n_part = n_part;
     ta.objective = objective;
+    ta.temper = static_cast<float>(temper);
+    ta.rec_weight = static_cast<float>(rec_weight);
     ta.theta = th.as<float>();
     ta.mc = mlp_consts(*net, target_N);
     ta.dN = static_cast<float>(dN);
-    ta.r_buf = rb.as<float>();
     ta.lw_theta = lwt.as<double>();
     ta.lw0 = l0.as<double>();
     ta.n_total = n_total;
@@ -1018,6 +1025,9 @@ int pyfpt_train_proposal(const pyfpt_instance *inst, uint64_t seed, const pyfpt_
     if (!(cfg->lr > 0) || !(cfg->beta1 >= 0 && cfg->beta1 < 1) || !(cfg->beta2 >= 0 && cfg->beta2 < 1) || !(cfg->eps > 0))
         return fail(PYFPT_EINVAL, "bad Adam constants");
     if (cfg->objective != 0 && cfg->objective != 1) return fail(PYFPT_EINVAL, "objective must be 0 or 1");
+    if (!(cfg->temper > 0.0f && cfg->temper <= 1.0f)) return fail(PYFPT_EINVAL, "temper must be in (0, 1]");
+    if (cfg->stride < 1 || (cfg->objective == 0 && cfg->stride != 1))
+        return fail(PYFPT_EINVAL, "stride must be >= 1 (and 1 for objective 0)");
     if (cfg->n_sample >= (1ull << 32)) return fail(PYFPT_EINVAL, "n_sample must be < 2^32");
     for (int j = 0; j < NET_N_PARAMS; ++j)
         if (!std::isfinite(theta[j])) return fail(PYFPT_EINVAL, "theta[%d] is not finite", j);
@@ -1112,17 +1122,20 @@ int pyfpt_train_proposal(const pyfpt_instance *inst, uint64_t seed, const pyfpt_
         }
         const uint32_t np = static_cast<uint32_t>(ids.size());
         std::vector<uint64_t> off(np + 1, 0);
-        for (uint32_t i = 0; i < np; ++i) off[i + 1] = off[i] + (hk[ids[i]] + cfg->group - 1) / cfg->group;
+        for (uint32_t i = 0; i < np; ++i) {
+            const uint64_t groups = (hk[ids[i]] + cfg->group - 1) / cfg->group;
+            off[i + 1] = off[i] + (groups + cfg->stride - 1) / cfg->stride;
+        }
         const uint64_t n_rec = off[np];
         R.n_records = n_rec;
         // 3. replay into records under the proposal that drew the runs
         Prepared P;
         if ((rc = prepare(&I, 1, P))) return rc;
-        DevBuf dt, doff, drec, rk, rlw, rst, rnr, rb, lwt, l0, c, ls, part;
+        DevBuf dt, doff, drec, rk, rlw, rst, rnr, lwt, l0, c, ls, part;
         const int n_part = backward_groups(n_rec);
         if ((rc = dt.alloc(8ull * np)) || (rc = doff.alloc(8ull * (np + 1))) || (rc = drec.alloc(16ull * n_rec)) ||
             (rc = rk.alloc(4ull * np)) || (rc = rlw.alloc(8ull * np)) || (rc = rst.alloc(4ull * np)) ||
-            (rc = rnr.alloc(8ull * np)) || (rc = rb.alloc(4ull * n_rec)) || (rc = lwt.alloc(8ull * np)) ||
+            (rc = rnr.alloc(8ull * np)) || (rc = lwt.alloc(8ull * np)) ||
             (rc = l0.alloc(8ull * np)) || (rc = c.alloc(8ull * np)) || (rc = ls.alloc(8)) ||
             (rc = part.alloc(4ull * NET_N_PARAMS * static_cast<uint64_t>(n_part))))
             return rc;
@@ -1130,7 +1143,7 @@ int pyfpt_train_proposal(const pyfpt_instance *inst, uint64_t seed, const pyfpt_
         HIP_TRY(hipMemcpyAsync(doff.p, off.data(), 8ull * (np + 1), hipMemcpyHostToDevice, stream), "upload offsets");
         HIP_TRY(hipMemcpyAsync(l0.p, lw0.data(), 8ull * np, hipMemcpyHostToDevice, stream), "upload lw0");
         HIP_TRY(hipEventRecord(ev[1], stream), "event");
-        if ((rc = records_device(P, seed_r, cfg->group, dt.as<uint64_t>(), np, doff.as<uint64_t>(), drec.as<TrainRec>(),
+        if ((rc = records_device(P, seed_r, cfg->group, cfg->stride, dt.as<uint64_t>(), np, doff.as<uint64_t>(), drec.as<TrainRec>(),
                                  rk.as<uint32_t>(), rlw.as<double>(), rst.as<int32_t>(), rnr.as<uint64_t>(), stream)))
             return rc;
         HIP_TRY(hipEventRecord(ev[2], stream), "event");
@@ -1154,10 +1167,11 @@ int pyfpt_train_proposal(const pyfpt_instance *inst, uint64_t seed, const pyfpt_
         ta.n_paths = static_cast<int32_t>(np);
         ta.n_part = n_part;
         ta.objective = cfg->objective;
+        ta.temper = cfg->temper;
+        ta.rec_weight = static_cast<float>(cfg->stride);
         ta.theta = th.as<float>();
         ta.mc = P.inst[0].mlp;
         ta.dN = P.inst[0].c.dN;
-        ta.r_buf = rb.as<float>();
         ta.lw_theta = lwt.as<double>();
         ta.lw0 = l0.as<double>();
         ta.n_total = static_cast<double>(ns);
@@ -1167,7 +1181,9 @@ int pyfpt_train_proposal(const pyfpt_instance *inst, uint64_t seed, const pyfpt_
         ta.grad = g.as<double>();
         HIP_TRY(hipEventRecord(ev[2], stream), "event");
         for (int step = 0; step < cfg->steps; ++step) {
-            HIP_TRY(launch_train_loss(ta, stream), "launch loss kernels");
+            // the cross-entropy weights c_i depend on w_0 only: the forward pass (ln w_theta and
+            // the weights) is needed once per round; log M2's weights change with theta
+            if (step == 0 || cfg->objective == 0) HIP_TRY(launch_train_loss(ta, stream), "launch loss kernels");
             if (step == 0) HIP_TRY(hipMemcpyAsync(&R.loss_first, ls.p, 8, hipMemcpyDeviceToHost, stream), "download loss");
             HIP_TRY(launch_train_grad(ta, stream), "launch gradient kernels");
             t_adam += 1;

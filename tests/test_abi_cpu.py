@@ -112,9 +112,11 @@ def test_training_and_combine_entry_points_reject_bad_input(lib):
     lw = np.zeros(2)
     st = np.zeros(2, np.int32)
     vp = lambda a: ctypes.c_void_p(a.ctypes.data)
-    assert L.pyfpt_proposal_records(ctypes.byref(inst), 0, vp(t), 2, 3, vp(off), vp(rec), vp(k), vp(lw), vp(st),
+    assert L.pyfpt_proposal_records(ctypes.byref(inst), 0, vp(t), 2, 3, 1, vp(off), vp(rec), vp(k), vp(lw), vp(st),
                                     ctypes.byref(opt)) == lib.PYFPT_EINVAL          # group 3
-    assert L.pyfpt_proposal_records(ctypes.byref(inst), 0, vp(t), 2, 4, vp(off), vp(rec), vp(k), vp(lw), vp(st),
+    assert L.pyfpt_proposal_records(ctypes.byref(inst), 0, vp(t), 2, 4, 0, vp(off), vp(rec), vp(k), vp(lw), vp(st),
+                                    ctypes.byref(opt)) == lib.PYFPT_EINVAL          # stride 0
+    assert L.pyfpt_proposal_records(ctypes.byref(inst), 0, vp(t), 2, 4, 1, vp(off), vp(rec), vp(k), vp(lw), vp(st),
                                     ctypes.byref(opt)) == lib.PYFPT_EINVAL          # offsets
     net = lib.pyfpt_mlp()
     net.hidden = 64
@@ -125,14 +127,18 @@ def test_training_and_combine_entry_points_reject_bad_input(lib):
     off2 = np.array([0, 1, 3], np.uint64)
     rec["pn"] = [(0 << 3) | 4, (1 << 3) | 4, (5 << 3) | 4]       # path index 5 >= n_paths
     assert L.pyfpt_proposal_loss_grad(ctypes.byref(net), 196.0, 1e-3, vp(theta), vp(rec), 3, vp(off2), 2, vp(lw), 10.0,
-                                      0, vp(loss), vp(grad), vp(lwt), ctypes.byref(opt)) == lib.PYFPT_EINVAL
+                                      0, 1.0, 1.0, vp(loss), vp(grad), vp(lwt), ctypes.byref(opt)) == lib.PYFPT_EINVAL
     rec["pn"] = [(0 << 3) | 4, (1 << 3) | 0, (1 << 3) | 4]       # zero steps in a group
     assert L.pyfpt_proposal_loss_grad(ctypes.byref(net), 196.0, 1e-3, vp(theta), vp(rec), 3, vp(off2), 2, vp(lw), 10.0,
-                                      0, vp(loss), vp(grad), vp(lwt), ctypes.byref(opt)) == lib.PYFPT_EINVAL
+                                      0, 1.0, 1.0, vp(loss), vp(grad), vp(lwt), ctypes.byref(opt)) == lib.PYFPT_EINVAL
     rec["pn"] = [(0 << 3) | 4, (1 << 3) | 4, (1 << 3) | 4]
     assert L.pyfpt_proposal_loss_grad(ctypes.byref(net), 196.0, 1e-3, vp(theta), vp(rec), 3, vp(off2), 2, vp(lw), 10.0,
-                                      2, vp(loss), vp(grad), vp(lwt), ctypes.byref(opt)) == lib.PYFPT_EINVAL  # objective
-    cfg = lib.pyfpt_train_config(10.0, 5.0, 100, 0, 1, 1, 4, 1e-3, 0.9, 0.999, 1e-8, 0, 0)   # lo > hi
+                                      2, 1.0, 1.0, vp(loss), vp(grad), vp(lwt), ctypes.byref(opt)) == lib.PYFPT_EINVAL  # objective
+    assert L.pyfpt_proposal_loss_grad(ctypes.byref(net), 196.0, 1e-3, vp(theta), vp(rec), 3, vp(off2), 2, vp(lw), 10.0,
+                                      1, 0.0, 1.0, vp(loss), vp(grad), vp(lwt), ctypes.byref(opt)) == lib.PYFPT_EINVAL  # temper
+    assert L.pyfpt_proposal_loss_grad(ctypes.byref(net), 196.0, 1e-3, vp(theta), vp(rec), 3, vp(off2), 2, vp(lw), 10.0,
+                                      0, 1.0, 4.0, vp(loss), vp(grad), vp(lwt), ctypes.byref(opt)) == lib.PYFPT_EINVAL  # strided log M2
+    cfg = lib.pyfpt_train_config(10.0, 5.0, 100, 0, 1, 1, 4, 1e-3, 0.9, 0.999, 1e-8, 0, 1.0, 1, 0)   # lo > hi
     inst.bias.kind = lib.BIAS_MLP
     bf = np.zeros(4481, np.uint16)
     rep = (lib.pyfpt_train_report * 1)()

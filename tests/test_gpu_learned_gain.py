@@ -4,7 +4,8 @@ phi_in = 6, reflecting wall at 8, dN = 1e-3), against the fixed noise-scaled bia
 The window (190, 202] lies near P ~ 1e-30.  With B = A S the weights of the runs that reach
 it spread over many decades (Sec. 3.1 notes this limit of a fixed bias), so a fixed A
 resolves it with a handful of effective samples.  A network trained with the cross-entropy
-objective through windows at N = 60, 100, 140 and 196 must (i) estimate P in the window in
+objective (window weights w_0^(1/2)) through windows at N = 60, 100, 140 and 196, 8000 window
+runs per round, must (i) estimate P in the window in
 agreement with the pole expansion (Sturm-Liouville solve of the oracle, end moved by
 beta S sqrt(dN) for the discrete monitoring) and (ii) reach a much larger effective sample
 size in the window than the best fixed bias from the same number of runs.
@@ -53,8 +54,8 @@ def test_learned_proposal_resolves_the_far_tail(fpt):
     for si, c in enumerate((60.0, 100.0, 140.0, 196.0)):
         print(f"[case] training stage N* = {c}", flush=True)
         theta, _, rep = fpt.train_proposal(dataclasses.replace(inst, target_N=c), 1 + 100 * si, theta,
-                                           window=(c - 6, c + 6), n_sample=100_000, rounds=3, steps=40,
-                                           max_paths=2000, lr=3e-3, objective=1)
+                                           window=(c - 6, c + 6), n_sample=200_000, rounds=3, steps=40,
+                                           max_paths=8000, lr=3e-3, objective=1, temper=0.5)
         for r in rep:
             print({k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()}, flush=True)
     learned = dataclasses.replace(inst, mlp=dataclasses.replace(p0, values=theta))

@@ -70,18 +70,20 @@ def test_records_learned_proposal_mostly_identical(fpt):
     assert same.mean() > 0.9
 
 
-@pytest.mark.parametrize("objective", [0, 1])
-def test_loss_and_gradient_match_oracle(fpt, objective):
+@pytest.mark.parametrize("objective,temper,stride", [(0, 1.0, 1), (1, 1.0, 1), (1, 0.5, 1), (1, 0.5, 4)])
+def test_loss_and_gradient_match_oracle(fpt, objective, temper, stride):
     base = W.c2(3000)[3]
     ids, k, lw = _pick(fpt, base, 6000, 60000, 40)
-    g = fpt.proposal_records(base, 0, ids, k, 4)
-    o = O.records(to_model(base), 0, ids, 4)
+    g = fpt.proposal_records(base, 0, ids, k, 4, stride)
+    o = O.records(to_model(base), 0, ids, 4, stride)
     assert g.rec.tobytes() == o.rec.tobytes()
     p = W.c4_params(7, scale=1.5, out_scale=0.8)
     theta = p.values_f32()
     inst = W.c4_instance(p, n_traj=1, stream=base.stream)
-    loss_g, grad_g, lwt_g = fpt.proposal_loss_grad(p, inst.target_N, base.dN, theta, g, g.lw, 3000.0, objective)
-    loss_o, grad_o, lwt_o = O.loss_grad(to_model(inst), theta.astype(np.float64), o, o.lw, 3000.0, objective)
+    loss_g, grad_g, lwt_g = fpt.proposal_loss_grad(p, inst.target_N, base.dN, theta, g, g.lw, 3000.0, objective, temper,
+                                                   float(stride))
+    loss_o, grad_o, lwt_o = O.loss_grad(to_model(inst), theta.astype(np.float64), o, o.lw, 3000.0, objective, temper,
+                                        float(stride))
     d_lw = np.abs(lwt_g - lwt_o)
     print(f"loss {loss_g:.6f} vs {loss_o:.6f}; max |d lw_theta| {d_lw.max():.2e}; "
           f"|grad| max {np.abs(grad_o).max():.3e}")

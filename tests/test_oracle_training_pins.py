@@ -118,3 +118,28 @@ def test_cross_entropy_gradient_and_closed_form():
         tm = theta.copy(); tm[j] -= h
         fd = (O.loss_grad(mm, tp, rec, rec.lw, 1e4, 1)[0] - O.loss_grad(mm, tm, rec, rec.lw, 1e4, 1)[0]) / (2 * h)
         assert abs(fd - grad[j]) <= 1e-6 * scale + 1e-5 * abs(grad[j]), (j, fd, grad[j])
+
+
+def test_record_stride_keeps_every_sth_group():
+    """With stride s the records are exactly the groups g = 0, s, 2s, ... of the complete records
+    (bit for bit); weighted by s, their sums estimate the complete sums."""
+    m = _fixed_model()
+    ids, _ = _short_paths(m, 6000, 40000, 8)
+    full = O.records(m, 0, ids, 4)
+    s4 = O.records(m, 0, ids, 4, stride=4)
+    for i in range(len(ids)):
+        f = full.rec[full.off[i]:full.off[i + 1]]
+        g = s4.rec[s4.off[i]:s4.off[i + 1]]
+        assert g.tobytes() == f[(f["k"] // 4) % 4 == 0].tobytes()
+    # a constant candidate: the strided estimate of ln w_theta agrees with the complete sum
+    net = W.MlpParams(np.zeros(4481, np.float32), out_scale=1.0)
+    mm = O.Model.from_instance(W.c4_instance(net, n_traj=1, stream=m.stream))
+    v = np.zeros(4481)
+    v[4480] = 0.6
+    _, _, lw_full = O.loss_grad(mm, v, full, full.lw, 1e4, objective=1)
+    _, _, lw_s4 = O.loss_grad(mm, v, s4, s4.lw, 1e4, objective=1, rec_weight=4.0)
+    # each group's term -c H + c^2 n dN/2 has spread ~ c sqrt(4 dN); the strided sum's error is
+    # ~ sqrt(3 G) c sqrt(4 dN) for G groups
+    G = np.diff(full.off.astype(np.int64))
+    tol = 5 * np.sqrt(3 * G) * 0.6 * np.sqrt(4 * float(np.float32(m.dN)))
+    assert np.all(np.abs(lw_s4 - lw_full) < tol)
