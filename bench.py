@@ -36,7 +36,7 @@ OPS_PER_STEP = 31 + 15 + 5 + 36
 # HBM bytes per launch of the step kernel on this workload: rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1
 # (factors read off a plain 1 GiB copy, `--copy-calibration`), summaries under profiles/.
 # Reset to None whenever the step kernel changes until the counters are taken again.
-TRAFFIC = 3.252e9
+TRAFFIC = None
 
 
 def parse():

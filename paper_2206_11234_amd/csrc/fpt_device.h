@@ -43,8 +43,9 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
         const uint32_t hi_a = static_cast<uint32_t>(pa >> 32);
         const uint32_t lo_b = static_cast<uint32_t>(pb);
         const uint32_t hi_b = static_cast<uint32_t>(pb >> 32);
-        const uint32_t n0 = hi_b ^ c1 ^ k0;
-        const uint32_t n2 = hi_a ^ c3 ^ k1;
+        // three-input xor in one v_bitop3_b32 (truth table 0x96 = a ^ b ^ c)
+        const uint32_t n0 = __builtin_amdgcn_bitop3_b32(hi_b, c1, k0, 0x96);
+        const uint32_t n2 = __builtin_amdgcn_bitop3_b32(hi_a, c3, k1, 0x96);
         c0 = n0;
         c1 = lo_b;
         c2 = n2;
@@ -172,6 +173,9 @@ struct F4 {
 };
 
 __device__ __forceinline__ F4 normals4(uint32_t j, uint64_t t, uint32_t stream, uint32_t key0, uint32_t key1) {
+    // the key schedule is recomputed by scalar adds at each call: left to itself the compiler
+    // hoists all twenty round keys into scalar registers and spills them to vector lanes
+    asm volatile("" : "+s"(key0), "+s"(key1));
     const U4 x = philox4x32_10(j, static_cast<uint32_t>(t), static_cast<uint32_t>(t >> 32), stream, key0, key1);
     F4 out;
     {
