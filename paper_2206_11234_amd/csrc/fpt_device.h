@@ -55,9 +55,11 @@ __device__ __forceinline__ U4 philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c
 }
 
 // u = (2 (x >> 9) + 1) 2^-24: odd multiples of 2^-24 in (0, 1), exact in binary32.
+// Formed as (1 + (x >> 9) 2^-23) + (2^-24 - 1): the first term is the float with exponent
+// bits of 1.0 and mantissa x >> 9, the constant is exact, and the sum, a multiple of 2^-24
+// below 1, is exact too.
 __device__ __forceinline__ float uniform24(uint32_t x) {
-    const uint32_t odd = ((x >> 9) << 1) | 1u;
-    return static_cast<float>(odd) * 0x1p-24f;
+    return __uint_as_float(0x3F800000u | (x >> 9)) + (0x1p-24f - 1.0f);
 }
 
 // 1/x for positive normal x: Newton-Raphson y <- fma(y, fma(-x, y, 1), y), three
@@ -254,13 +256,22 @@ __device__ __forceinline__ float bias_ratio(const StepConsts &C, float phi, floa
     }
 }
 
+// Status of a run that has stopped, from where it stopped: the end surface takes precedence
+// over the step cap, the cap over escape (Sec. 2.1, Sec. 3).
+__device__ __forceinline__ int final_status(const StepConsts &C, float phi, uint32_t k) {
+    if (phi <= C.phi_end) return ST_ENDED;
+    if (k >= C.k_max) return ST_CENSORED;
+    return (phi > C.phi_esc) ? ST_ESCAPED : ST_RUNNING;
+}
+
 // One Euler-Maruyama step of the biased Langevin equation (Sec. 2.2 eq. eq_euler_maruyam_modified,
 // drift, noise and bias at the pre-step point), the weight increment
 // -r (r dN/2 + sqrt(dN) xi) accumulated in binary64, reflection above phi_UV, and the end /
-// cap / escape tests (Sec. 2.1, Sec. 3).  r_net is the bias when it comes from the learned
+// cap / escape tests (Sec. 2.1, Sec. 3).  run stays true while none of the three tests fires;
+// final_status() names the one that did.  r_net is the bias when it comes from the learned
 // network.  Returns r and writes sqrt(dN) xi, which the training replay reuses.
 template <int POT, int BIAS>
-__device__ __forceinline__ float em_step(const StepConsts &C, float &phi, uint32_t &k, double &lw, int &st, float xi,
+__device__ __forceinline__ float em_step(const StepConsts &C, float &phi, uint32_t &k, double &lw, bool &run, float xi,
                                          float r_net, float &sxi) {
     float D, S;
     drift_noise<POT>(C, phi, D, S);
@@ -282,12 +293,12 @@ __device__ __forceinline__ float em_step(const StepConsts &C, float &phi, uint32
         const float dlw = -(r * inc);
         lw += static_cast<double>(dlw);
     }
-    nphi = (nphi > C.phi_uv) ? C.two_uv - nphi : nphi;
-    phi = nphi;
+    // Reflection x -> 2 phi_UV - x above the wall, as a minimum: 2 phi_UV is exact and rounding
+    // is monotone, so fl(2 phi_UV - x) <= phi_UV < x exactly when x > phi_UV (and >= x otherwise);
+    // with no wall 2 phi_UV is +inf and the minimum is x.
+    phi = __builtin_fminf(nphi, C.two_uv - nphi);
     k += 1;
-    const int st_esc = (phi > C.phi_esc) ? ST_ESCAPED : ST_RUNNING;
-    const int st_cap = (k >= C.k_max) ? ST_CENSORED : st_esc;
-    st = (phi <= C.phi_end) ? ST_ENDED : st_cap;
+    run = !(phi <= C.phi_end) && (k < C.k_max) && !(phi > C.phi_esc);
     return r;
 }
 

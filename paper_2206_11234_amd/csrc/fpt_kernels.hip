@@ -157,7 +157,7 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
     uint32_t k = 0;
     double lw = 0.0;
     uint64_t t = 0;
-    int st = ST_RUNNING;
+    bool run = false;
     bool active = false;
     bool need = true;
     LaneAcc acc;
@@ -240,7 +240,7 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
                     phi = C.phi_in;
                     k = 0;
                     lw = 0.0;
-                    st = ST_RUNNING;
+                    run = true;
                     active = true;
                 } else {
                     active = false;
@@ -251,14 +251,14 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
 
         // ---- four Euler-Maruyama steps from one Philox call
         float sxi;
-        auto step = [&](float xi, float r_net) { (void)em_step<POT, BIAS>(C, phi, k, lw, st, xi, r_net, sxi); };
+        auto step = [&](float xi, float r_net) { (void)em_step<POT, BIAS>(C, phi, k, lw, run, xi, r_net, sxi); };
         if constexpr (BIAS != BIAS_MLP) {
             if (active) {
                 const F4 z = normals4(k >> 2, t, stream, a.key0, a.key1);
                 const float zs[4] = {z.a, z.b, z.c, z.d};
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    if (st == ST_RUNNING) step(zs[s], 0.0f);
+                    if (run) step(zs[s], 0.0f);
                 }
             }
         } else {
@@ -270,13 +270,14 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 if (s > 0 && a.mlp_every == 1) r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
-                if (active && st == ST_RUNNING) step(zs[s], r_mlp);
+                if (active && run) step(zs[s], r_mlp);
             }
         }
 
         // ---- retire finished runs into the workgroup table
-        const bool fin = active && st != ST_RUNNING;
+        const bool fin = active && !run;
         if (fin) {
+            const int st = final_status(C, phi, k);
             uint32_t rl;
             if (st == ST_ENDED) {
                 const uint32_t *K = a.thr + thr_base;

@@ -55,22 +55,22 @@ __global__ __launch_bounds__(256) void fpt_record_kernel(RecordArgs a) {
     float phi = C.phi_in;
     uint32_t k = 0;
     double lw = 0.0;
-    int st = have ? ST_RUNNING : ST_ENDED;
+    bool run = have;
     float H = 0.0f, phi_e = phi;
     uint32_t k_e = 0, n_e = 0;
     uint64_t n_rec = 0;
-    while (__any(st == ST_RUNNING)) {
+    while (__any(run)) {
         float r_mlp = 0.0f;
         if constexpr (BIAS == BIAS_MLP) r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
         F4 z{};
-        if (st == ST_RUNNING) z = normals4(k >> 2, t, a.inst.stream, a.key0, a.key1);
+        if (run) z = normals4(k >> 2, t, a.inst.stream, a.key0, a.key1);
         const float zs[4] = {z.a, z.b, z.c, z.d};
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             if constexpr (BIAS == BIAS_MLP) {
                 if (s > 0 && a.mlp_every == 1) r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
             }
-            if (st == ST_RUNNING) {
+            if (run) {
                 if ((k & emask) == 0) {
                     phi_e = phi;
                     k_e = k;
@@ -78,10 +78,10 @@ __global__ __launch_bounds__(256) void fpt_record_kernel(RecordArgs a) {
                     n_e = 0;
                 }
                 float sxi;
-                const float r = em_step<POT, BIAS>(C, phi, k, lw, st, zs[s], r_mlp, sxi);
+                const float r = em_step<POT, BIAS>(C, phi, k, lw, run, zs[s], r_mlp, sxi);
                 H = H + __builtin_fmaf(r, C.dN, sxi);
                 n_e += 1;
-                if ((k & emask) == 0 || st != ST_RUNNING) {
+                if ((k & emask) == 0 || !run) {
                     const uint32_t grp = k_e / static_cast<uint32_t>(a.group);
                     if (grp % static_cast<uint32_t>(a.stride) == 0 && n_rec < cap) {
                         TrainRec R;
@@ -99,7 +99,7 @@ __global__ __launch_bounds__(256) void fpt_record_kernel(RecordArgs a) {
     if (have) {
         a.k_out[i] = k;
         a.lw_out[i] = lw;
-        a.st_out[i] = st;
+        a.st_out[i] = final_status(C, phi, k);
         a.n_rec_out[i] = n_rec;
     }
 }
