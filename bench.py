@@ -31,8 +31,9 @@ PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
 # binary32/binary64/integer operation of the step semantics counts once (fma = 1):
 #   step 27 (Newton reciprocal 7, drift/noise/bias 6, EM update 3, weight 6, wall 2, k 1, tests 3)
 #   Philox 60/4 (two 32x32->64 multiplies and four xors per round, ten rounds per 4 steps)
-#   uniforms 12/4 (shift, or, add), Box-Muller 72/2 (log 29, -2L 1, sqrt 13, sincos 27, rho*cos/sin 2).
-OPS_PER_STEP = 27 + 15 + 3 + 36
+#   radius uniforms 6/4 (shift, or, add), Box-Muller 134/4 (log 25, -2L 1, sqrt 13,
+#   sincos 26 with the quadrant taken from the Philox word, rho*cos/sin 2).
+OPS_PER_STEP = 27 + 15 + 1.5 + 33.5
 # HBM bytes per launch of the step kernel on this workload: rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1
 # (factors read off a plain 1 GiB copy, `--copy-calibration`), summaries under profiles/.
 # Reset to None whenever the step kernel changes until the counters are taken again.

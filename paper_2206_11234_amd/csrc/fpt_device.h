@@ -90,18 +90,14 @@ __device__ __forceinline__ float sqrt_f32(float x) {
     return x * y;
 }
 
-// ln x for positive normal x: x = 2^e f, f in [sqrt(1/2), sqrt 2];
-// ln f = 2 atanh(s), s = (f-1)/(f+1), as the odd series to s^9;
-// ln x = e ln2_hi + (e ln2_lo + ln f).
+// ln x for positive normal x: x = 2^e f with f in (sqrt(1/2), sqrt 2], bit patterns
+// (0x3F3504F3, 0x3FB504F3]; ln f = 2 atanh(s), s = (f-1)/(f+1), as the odd series to s^9;
+// ln x = e ln2_hi + (e ln2_lo + ln f).  The split is done on the bits: b - 0x3F3504F4 has e
+// in its arithmetic-shifted top bits and f - 0x3F3504F4 in its low 23.
 __device__ __forceinline__ float log_f32(float x) {
-    const uint32_t b = __float_as_uint(x);
-    int e = static_cast<int>(b >> 23) - 127;
-    const uint32_t mant = b & 0x007FFFFFu;
-    float f = __uint_as_float(mant | 0x3F800000u);
-    if (f > 1.41421354f) {
-        f = __uint_as_float(mant | 0x3F000000u);
-        e += 1;
-    }
+    const int32_t ix = static_cast<int32_t>(__float_as_uint(x) - 0x3F3504F4u);
+    const int e = ix >> 23;
+    const float f = __uint_as_float((static_cast<uint32_t>(ix) & 0x007FFFFFu) + 0x3F3504F4u);
     const float s = (f - 1.0f) * recip_f32(f + 1.0f);
     const float z = s * s;
     float p = 1.0f / 9.0f;
@@ -117,12 +113,16 @@ __device__ __forceinline__ float log_f32(float x) {
     return __builtin_fmaf(ef, ln2_hi, __builtin_fmaf(ef, ln2_lo, lf));
 }
 
-// cos(2 pi u), sin(2 pi u) for u in [0, 1] a multiple of 2^-24: nearest quarter q,
-// r = u - q/4 in [-1/8, 1/8] (exact), Taylor polynomials of sin(2 pi r) to r^9 and
-// cos(2 pi r) to r^10 with coefficients (+-)(2 pi)^n/n!, then a quarter-turn rotation.
-__device__ __forceinline__ void sincos2pi_f32(float u, float &c_out, float &s_out) {
-    const float q = __builtin_rintf(u * 4.0f);
-    const float r = u - q * 0.25f;
+// cos(2 pi u), sin(2 pi u) for the uniform u = uniform24(x): nearest quarter q = rint(4u),
+// r = u - q/4 in [-1/8, 1/8], Taylor polynomials of sin(2 pi r) to r^9 and cos(2 pi r) to r^10
+// with coefficients (+-)(2 pi)^n/n!, then a quarter-turn rotation by q.
+// q and r come from the bits of x: with y = x + 2^29 (mod 2^32), q = y >> 30 (mod 4) and
+// r = (2 a + 1 - 2^21) 2^-24 for a = bits 9..29 of y, formed exactly as
+// (0.5 + (2a + 1) 2^-24) - 0.625 -- the same values as the float reduction of u, for every x.
+__device__ __forceinline__ void sincos2pi_bits(uint32_t x, float &c_out, float &s_out) {
+    const uint32_t y = x + 0x20000000u;
+    const uint32_t a = (y >> 9) & 0x1FFFFFu;
+    const float r = __uint_as_float(0x3F000001u | (a << 1)) - 0.625f;
     const float r2 = r * r;
     float ps = __builtin_fmaf(42.058693944897653145f, r2, -76.7058597530613858416f);
     ps = __builtin_fmaf(ps, r2, 81.6052492760750542034f);
@@ -134,14 +134,14 @@ __device__ __forceinline__ void sincos2pi_f32(float u, float &c_out, float &s_ou
     pc = __builtin_fmaf(pc, r2, 64.939394022668291491f);
     pc = __builtin_fmaf(pc, r2, -19.7392088021787172377f);
     const float cs = __builtin_fmaf(pc, r2, 1.0f);
-    // quarter-turn rotation by q, branch-free: odd q swaps (cos, sin); the signs of
-    // cos and sin flip for q = 1, 2 and q = 2, 3 respectively (IEEE negation = sign bit)
-    const uint32_t iq = static_cast<uint32_t>(static_cast<int>(q)) & 3u;
-    const bool swap = (iq & 1u) != 0u;
+    // quarter-turn rotation by q = y >> 30, branch-free: odd q swaps (cos, sin); cos changes
+    // sign for q = 1, 2 (bit 31 of y + 2^30) and sin for q = 2, 3 (bit 31 of y); IEEE negation
+    // is the sign bit
+    const bool swap = (y & 0x40000000u) != 0u;
     const float c0 = swap ? sn : cs;
     const float s0 = swap ? cs : sn;
-    const uint32_t sign_c = ((iq + 1u) & 2u) << 30;
-    const uint32_t sign_s = (iq & 2u) << 30;
+    const uint32_t sign_c = (y + 0x40000000u) & 0x80000000u;
+    const uint32_t sign_s = y & 0x80000000u;
     c_out = __uint_as_float(__float_as_uint(c0) ^ sign_c);
     s_out = __uint_as_float(__float_as_uint(s0) ^ sign_s);
 }
@@ -182,19 +182,17 @@ __device__ __forceinline__ F4 normals4(uint32_t j, uint64_t t, uint32_t stream, 
     F4 out;
     {
         const float ua = uniform24(x.x);
-        const float ub = uniform24(x.y);
         const float rho = sqrt_f32(-2.0f * log_f32(ua));
         float c, s;
-        sincos2pi_f32(ub, c, s);
+        sincos2pi_bits(x.y, c, s);
         out.a = rho * c;
         out.b = rho * s;
     }
     {
         const float ua = uniform24(x.z);
-        const float ub = uniform24(x.w);
         const float rho = sqrt_f32(-2.0f * log_f32(ua));
         float c, s;
-        sincos2pi_f32(ub, c, s);
+        sincos2pi_bits(x.w, c, s);
         out.c = rho * c;
         out.d = rho * s;
     }
