@@ -27,17 +27,18 @@ if ROOT not in sys.path:
 # the chip: 32-bit add/mul/logic/move issue at 32 lanes per clock per SIMD, fma, 32x32 integer
 # multiplies, f64 add and conversions at 16 (they occupy two issue slots).
 PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
-# Algorithmic lane operations per trajectory-step of the quadratic, noise-scaled path: every
-# binary32/binary64/integer operation of the step semantics counts once (fma = 1):
+# Algorithmic lane operations per trajectory-step of the quadratic, noise-scaled path, counted
+# as the fewest gfx950 VALU instructions the step semantics needs (fma = 1, three-input xor = 1,
+# 32x32->64 multiply = 1):
 #   step 27 (Newton reciprocal 7, drift/noise/bias 6, EM update 3, weight 6, wall 2, k 1, tests 3)
-#   Philox 60/4 (two 32x32->64 multiplies and four xors per round, ten rounds per 4 steps)
-#   radius uniforms 6/4 (shift, or, add), Box-Muller 134/4 (log 25, -2L 1, sqrt 13,
-#   sincos 26 with the quadrant taken from the Philox word, rho*cos/sin 2).
-OPS_PER_STEP = 27 + 15 + 1.5 + 33.5
+#   Philox 40/4 (two 32x32->64 multiplies and two three-input xors per round, ten rounds per 4 steps)
+#   radius uniforms 6/4 (shift, or, add), Box-Muller 128/4 (log 25, -2L 1, sqrt 13,
+#   sincos 23 with the quadrant taken from the Philox word, rho*cos/sin 2).
+OPS_PER_STEP = 27 + 10 + 1.5 + 32
 # HBM bytes per launch of the step kernel on this workload: rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1
 # (factors read off a plain 1 GiB copy, `--copy-calibration`), summaries under profiles/.
 # Reset to None whenever the step kernel changes until the counters are taken again.
-TRAFFIC = None
+TRAFFIC = (602499.5 * 1048576 / 524302.4 + 2744400.1 * 1.0) * 1024
 
 
 def parse():
@@ -72,6 +73,8 @@ def parse():
     p.add_argument("--c5", action="store_true",
                    help="the large bump-potential run as one multi-bias batch, combined bin by bin")
     p.add_argument("--c5-total", type=int, default=1_000_000_000)
+    p.add_argument("--c3", action="store_true",
+                   help="the 64-instance batched sweep in one graph-replayed launch with the autotuned shape")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only copy 1 GiB device-to-device 3 times (scale reference for HBM byte counters)")
     return p.parse_args()
@@ -239,6 +242,45 @@ def learned_gain(args):
     print(json.dumps(out), flush=True)
 
 
+def c3_run(args):
+    """The batched sweep (64 instances of uneven length, 1e6 runs each) as one persistent launch,
+    replayed from a HIP graph, launch shape and queue chunk from the library's autotuner."""
+    import torch
+    import paper_2206_11234_amd as F
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    insts = W.c3(args.n_traj)
+    side = torch.cuda.Stream()   # graph capture needs a non-null stream
+    kw = dict(block=0, wg_per_cu=0, chunk=0)
+    with torch.cuda.stream(side):
+        # the first call runs the autotuner; one timed pass gives the kernel time (HIP events)
+        _, _, tm = F.run_batch(insts, 0, timing=True, **kw)
+        for _ in range(args.warmup):
+            F.run_batch(insts, 0, use_graph=True, **kw)
+        side.synchronize()
+        steps_total = 0
+        t_all = time.perf_counter()
+        for s in range(args.steps):
+            t0 = time.perf_counter()
+            results, _, _ = F.run_batch(insts, 0, use_graph=True, **kw)
+            side.synchronize()
+            steps_total += sum(r.total_steps for r in results)
+            print(f"[c3] pass {s} {(time.perf_counter() - t0) * 1e3:.1f} ms", file=sys.stderr, flush=True)
+        wall = time.perf_counter() - t_all
+    steps_per_pass = steps_total / args.steps
+    lens = [r.total_steps / i.n_traj for r, i in zip(results, insts)]
+    out = {"metric": "weighted traj-steps/s", "value": steps_total / wall, "unit": "traj-steps/s",
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+           "kernel_ms": tm[0], "kernel_rate": steps_per_pass / (tm[0] / 1e3),
+           "config": {"workload": "C3 batched sweep: 64 instances from splitmix64(0), phi_in~U[3,12], "
+                                  "m in {0.01,0.1,0.5,1}, A in {0..6}, wall on/off, dN in {1e-3,5e-4}, "
+                                  "1e6 runs each, one graph-replayed launch, autotuned shape",
+                      "instances": len(insts), "runs_per_instance": args.n_traj, "steps_per_pass": steps_per_pass,
+                      "mean_len_min": min(lens), "mean_len_max": max(lens)}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -252,6 +294,9 @@ def main():
         return
     if args.c5:
         c5_run(args)
+        return
+    if args.c3:
+        c3_run(args)
         return
     import numpy as np
     import torch
