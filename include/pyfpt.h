@@ -266,7 +266,11 @@ int pyfpt_mlp_forward(const pyfpt_mlp *mlp, double target_N, const float *phi, c
  *   estimator 1: lognormal P_hat (log_p_ln) with u = log(1 + rel_err_ln_hi) as the error of
  *                log P; trusted when n_j >= 8 and the bin's normality p-value >= 0.005;
  *   estimator 2: per result, estimator 1 when the result passes the lognormal gate (no bin with
- *                a defined p-value below 0.005, Sec. 2.4), else estimator 0.
+ *                a defined p-value below 0.005, Sec. 2.4), else estimator 0;
+ *   estimator 3: per bin, estimator 1 where the bin passes the gate (n_j >= 8, p >= 0.005),
+ *                else estimator 0 with its own trust rule (the fallback of Sec. 2.4 taken bin
+ *                by bin: with many runs per bin the test resolves the departure from a
+ *                lognormal of wide bins and a whole-result gate rejects nearly every result).
  * res: n_res results (host or device buffers, as each one's on_device says).  Outputs (host,
  * n_bins each): log_p (NaN where nothing contributes), err_log (standard error of log P),
  * n_used (contributing results).  Host arithmetic; EINVAL for bad arguments.

@@ -424,7 +424,9 @@ def combine(hists, estimator: int = 2):
     error of log P = the jackknife relative error, trusted if n_j > 400 and n_j > exp(sigma^2);
     1: lognormal P_hat, error u = log(1 + rel_hi), trusted if n_j >= 8 and p >= 0.005; 2: the
     lognormal estimator for a histogram that passes the gate in every bin with a p-value, else
-    the naive one.  Returns (log_p, err_log, n_used)."""
+    the naive one; 3: bin by bin, the lognormal estimate where that bin passes the gate
+    (n_j >= 8, p >= 0.005), else the naive one under its own rule -- the fallback of Sec. 2.4
+    taken per bin.  Returns (log_p, err_log, n_used)."""
     B = len(hists[0].edges) - 1
     sw = np.zeros(B)
     swy = np.zeros(B)
@@ -435,16 +437,20 @@ def combine(hists, estimator: int = 2):
         if est == 2:
             est = 1 if not np.any(np.isfinite(pv) & (pv < 0.005)) else 0
         n = h.count[:B].astype(np.float64)
+        y0 = h.log_p_naive()
+        e0 = h.jackknife_rel_err()
+        with np.errstate(over="ignore", invalid="ignore"):
+            ok0 = (n > 400) & (n > np.exp(h.m2_lnw[:B]))
+        y1, _, hi = h.lognormal()
+        e1 = np.log1p(hi)
+        with np.errstate(invalid="ignore"):
+            ok1 = (n >= 8) & np.isfinite(pv) & (pv >= 0.005)
         if est == 0:
-            y = h.log_p_naive()
-            e = h.jackknife_rel_err()
-            with np.errstate(over="ignore", invalid="ignore"):
-                ok = (n > 400) & (n > np.exp(h.m2_lnw[:B]))
+            y, e, ok = y0, e0, ok0
+        elif est == 1:
+            y, e, ok = y1, e1, ok1
         else:
-            y, _, hi = h.lognormal()
-            e = np.log1p(hi)
-            with np.errstate(invalid="ignore"):
-                ok = (n >= 8) & np.isfinite(pv) & (pv >= 0.005)
+            y, e, ok = np.where(ok1, y1, y0), np.where(ok1, e1, e0), ok1 | ok0
         with np.errstate(invalid="ignore"):
             ok &= np.isfinite(y) & np.isfinite(e) & (e > 0)
         w = np.where(ok, 1.0 / np.where(ok, e, 1.0) ** 2, 0.0)

@@ -857,7 +857,7 @@ int pyfpt_mlp_forward(const pyfpt_mlp *mlp, double target_N, const float *phi, c
 int pyfpt_combine(const pyfpt_result *res, int32_t n_res, int32_t n_bins, int32_t n_sub, int32_t estimator,
                   double *log_p, double *err_log, int32_t *n_used) {
     if (!res || !log_p || !err_log || !n_used || n_res < 1) return fail(PYFPT_EINVAL, "NULL argument or n_res < 1");
-    if (estimator < 0 || estimator > 2) return fail(PYFPT_EINVAL, "estimator must be 0, 1 or 2");
+    if (estimator < 0 || estimator > 3) return fail(PYFPT_EINVAL, "estimator must be 0, 1, 2 or 3");
     if (n_bins < 1) return fail(PYFPT_EINVAL, "n_bins must be >= 1");
     if (n_sub == 0) n_sub = kDefaultNsub;
     if (n_sub < 2 || n_sub > 64) return fail(PYFPT_EINVAL, "n_sub must be 0 or 2..64");
@@ -890,18 +890,15 @@ int pyfpt_combine(const pyfpt_result *res, int32_t n_res, int32_t n_bins, int32_
         }
         for (uint32_t j = 0; j < B; ++j) {
             const double n = static_cast<double>(C[L.count + j]);
-            double y = NAN, e = NAN;
-            bool ok = false;
-            if (est == 0) {
-                y = V[L.log_p + j];
-                e = V[L.rel_err_jk + j];
-                ok = n > 400.0 && n > std::exp(V[L.m2_lnw + j]);
-            } else {
-                y = V[L.log_p_ln + j];
-                e = std::log1p(V[L.rel_err_ln_hi + j]);
-                const double p = V[L.normal_p + j];
-                ok = n >= 8.0 && std::isfinite(p) && p >= 0.005;
-            }
+            // naive estimate, trusted when n > 400 and n > exp(var ln w); lognormal estimate,
+            // trusted when the bin passes the normality gate
+            const double p = V[L.normal_p + j];
+            const bool gate = n >= 8.0 && std::isfinite(p) && p >= 0.005;
+            const bool naive_ok = n > 400.0 && n > std::exp(V[L.m2_lnw + j]);
+            const bool use_ln = est == 1 || (est == 3 && gate);
+            const double y = use_ln ? V[L.log_p_ln + j] : V[L.log_p + j];
+            const double e = use_ln ? std::log1p(V[L.rel_err_ln_hi + j]) : V[L.rel_err_jk + j];
+            const bool ok = est == 0 ? naive_ok : (est == 1 ? gate : gate || naive_ok);
             if (!ok || !std::isfinite(y) || !std::isfinite(e) || !(e > 0)) continue;
             const double w = 1.0 / (e * e);
             sw[j] += w;

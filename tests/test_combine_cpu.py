@@ -48,6 +48,23 @@ def test_duplicates_and_single_contributors(hists):
     assert np.max(np.nonzero(u > 0)[0]) > np.max(np.nonzero(direct)[0])
 
 
+def test_per_bin_fallback_takes_each_bins_own_estimator(hists):
+    """Estimator 3: a bin that passes the normality gate takes the lognormal estimate, any other
+    bin the naive one under the naive trust rule (Sec. 2.4, applied bin by bin)."""
+    for h in hists:
+        lp3, e3, u3 = O.combine([h], 3)
+        lp1, e1, u1 = O.combine([h], 1)
+        lp0, e0, u0 = O.combine([h], 0)
+        assert np.array_equal(u3 > 0, (u1 > 0) | (u0 > 0))
+        ln = u1 > 0
+        assert np.array_equal(lp3[ln], lp1[ln]) and np.array_equal(e3[ln], e1[ln])
+        nv = (u0 > 0) & ~ln
+        assert np.array_equal(lp3[nv], lp0[nv]) and np.array_equal(e3[nv], e0[nv])
+    # with both kinds of bins present somewhere, the union reaches at least as far as either
+    lp, e, u = O.combine(hists, 3)
+    assert (u > 0).sum() >= max((O.combine(hists, k)[2] > 0).sum() for k in (0, 1))
+
+
 def _pack(lib, h, n_sub):
     B = len(h.edges) - 1
     R = B + 4
@@ -66,7 +83,7 @@ def _pack(lib, h, n_sub):
     return c, v
 
 
-@pytest.mark.parametrize("estimator", [0, 1, 2])
+@pytest.mark.parametrize("estimator", [0, 1, 2, 3])
 def test_library_combination_matches_oracle(hists, estimator):
     from paper_2206_11234_amd import _lib as lib
     bufs = [_pack(lib, h, 16) for h in hists]
