@@ -57,13 +57,15 @@ def parse():
     p.add_argument("--autotune", action="store_true")
     p.add_argument("--learned", action="store_true",
                    help="learned proposal vs the fixed-bias scan at equal error in the far-tail window")
-    p.add_argument("--n-eval", type=int, default=1_000_000)
+    p.add_argument("--n-eval", type=int, default=10_000_000)
     p.add_argument("--n-sample", type=int, default=200_000)
     p.add_argument("--rounds", type=int, default=3)
     p.add_argument("--train-steps", type=int, default=40)
     p.add_argument("--max-paths", type=int, default=8000)
     p.add_argument("--lr", type=float, default=3e-3)
     p.add_argument("--target", type=float, default=196.0)
+    p.add_argument("--eval-every", type=int, default=16,
+                   help="steps the learned bias is held for (1, 4, 8 or 16); training records use the same groups")
     p.add_argument("--objective", type=int, default=1, help="0: log M2, 1: cross entropy")
     p.add_argument("--temper", type=float, default=0.5, help="w_0^temper in the path weights")
     p.add_argument("--train-seed", type=int, default=1)
@@ -225,7 +227,7 @@ def learned_gain(args):
     v[:4480] = np.random.default_rng(0).normal(0.0, 1e-2, 4480)
     v[4480] = 1.0
     p0 = W.MlpParams(W.bf16_round(v), in_mean=(5.0, args.target, args.target), in_inv_scale=(0.4, 0.005, 0.01),
-                     out_scale=1.0, eval_every=4)
+                     out_scale=1.0, eval_every=args.eval_every)
     inst0 = W.c4_instance(p0, n_traj=args.n_eval, target_N=args.target, stream=base.stream)
     inst0 = dataclasses.replace(inst0, edges=edges)
     torch.cuda.synchronize()
@@ -245,7 +247,8 @@ def learned_gain(args):
             print(f"[learned] train round: {json.dumps(r)}", file=sys.stderr, flush=True)
         rep += r_stage
     train_s = time.perf_counter() - t0
-    p1 = W.MlpParams(theta, in_mean=p0.in_mean, in_inv_scale=p0.in_inv_scale, out_scale=1.0, eval_every=4)
+    p1 = W.MlpParams(theta, in_mean=p0.in_mean, in_inv_scale=p0.in_inv_scale, out_scale=1.0,
+                     eval_every=args.eval_every)
     learned = evaluate(dataclasses.replace(inst0, mlp=p1), "learned", block=256, wg_per_cu=1, chunk=1)
     # a fixed bias is a candidate only where its window estimate is trusted by the paper's
     # n_j > 400 criterion (Sec. 2.1); with fewer runs its error estimate is itself unreliable

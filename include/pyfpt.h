@@ -89,14 +89,14 @@ typedef struct pyfpt_potential {
  * `params` (device memory) holds the 4481 parameters as bfloat16, in this order:
  *   W1[64][3], b1[64], W2[64][64], b2[64], w3[64], b3        (row-major, W[out][in]).
  * The network is evaluated on the matrix cores with binary32 accumulation and bfloat16
- * activations, every step (eval_every = 1) or once per group of four steps at the group's
- * first step (eval_every = 4; the bias is then held for the group). */
+ * activations, every step (eval_every = 1) or once per group of 4, 8 or 16 steps at the
+ * group's first step (eval_every = 4, 8 or 16; the bias is then held for the group). */
 typedef struct pyfpt_mlp {
     const void *params;              /* device pointer, 4481 bfloat16 */
     int32_t hidden;                  /* must be 64 */
     float in_mean[3], in_inv_scale[3];
     float out_scale;
-    int32_t eval_every;              /* 1 or 4 */
+    int32_t eval_every;              /* 1, 4, 8 or 16 */
 } pyfpt_mlp;
 
 typedef struct pyfpt_bias {
@@ -288,13 +288,13 @@ int pyfpt_combine(const pyfpt_result *res, int32_t n_res, int32_t n_bins, int32_
  * w_theta,i is the weight the same path would have under the candidate network theta.  With
  * eta_k = r_0,k dN + sqrt(dN) xi_k, the noise increment of step k under the target process,
  * ln w_theta = sum_k [ -r_theta,k eta_k + r_theta,k^2 dN/2 ].  The candidate is held over
- * groups of `group` (1 or 4) steps, so each path reduces to one record per group.
+ * groups of `group` (1, 4, 8 or 16) steps, so each path reduces to one record per group.
  */
 typedef struct pyfpt_record {
     float phi;                       /* field before the group's first step */
     uint32_t k;                      /* step index of the group's first step */
     float H;                         /* sum over the group of fma(r_0, dN, sqrt(dN) xi), binary32 in step order */
-    uint32_t path_n;                 /* path index << 3 | number of steps in the group (1..4) */
+    uint32_t path_n;                 /* path index << 5 | number of steps in the group (1..16) */
 } pyfpt_record;
 
 /*
@@ -303,8 +303,9 @@ typedef struct pyfpt_record {
  * writes rec[rec_off[i] .. rec_off[i+1]), which must be its records: with stride s >= 1 only the
  * groups g = 0, s, 2s, ... are kept, ceil(ceil(k_i / group) / s) records.  All
  * arrays are host memory; k_out, lw_out and status_out receive the replayed run (identical to
- * the sampled one), so a caller can check the slots.  EINVAL: group not 1 or 4, rec_off not
- * ascending, stride < 1, or the instance as in pyfpt_run.  The call synchronises.
+ * the sampled one), so a caller can check the slots.  EINVAL: group not 1, 4, 8 or 16,
+ * n_paths >= 2^27, rec_off not ascending, stride < 1, or the instance as in pyfpt_run.  The
+ * call synchronises.
  */
 int pyfpt_proposal_records(const pyfpt_instance *inst, uint64_t seed, const uint64_t *t_ids, int32_t n_paths,
                            int32_t group, int32_t stride, const uint64_t *rec_off, pyfpt_record *rec,
@@ -325,8 +326,8 @@ int pyfpt_proposal_records(const pyfpt_instance *inst, uint64_t seed, const uint
  * out_scale (its params are not read); dN as in the sampling run; lw0[i] = ln w_0 of path i;
  * n_total = number of runs drawn.  Outputs: *loss, grad[4481] (binary64), lw_theta[n_paths].
  * The network is evaluated in binary32 without roundings (the training copy); the gradient is
- * summed in a fixed order.  EINVAL: n_paths < 1, rec_off not ascending to n_rec, a record's
- * path index >= n_paths or its step count outside 1..4.  The call synchronises.
+ * summed in a fixed order.  EINVAL: n_paths < 1 or >= 2^27, rec_off not ascending to n_rec, a
+ * record's path index >= n_paths or its step count outside 1..16.  The call synchronises.
  */
 int pyfpt_proposal_loss_grad(const pyfpt_mlp *net, double target_N, double dN, const float *theta,
                              const pyfpt_record *rec, uint64_t n_rec, const uint64_t *rec_off, int32_t n_paths,
@@ -337,10 +338,10 @@ int pyfpt_proposal_loss_grad(const pyfpt_mlp *net, double target_N, double dN, c
 typedef struct pyfpt_train_config {
     double window_lo, window_hi;     /* target window B* = (lo, hi] in N */
     uint64_t n_sample;               /* runs drawn per round from the current proposal */
-    int32_t max_paths;               /* window runs kept per round (0 = all) */
+    int32_t max_paths;               /* window runs kept per round (0 = all, up to 2^27 - 1) */
     int32_t rounds;                  /* sampling rounds */
     int32_t steps;                   /* Adam steps per round */
-    int32_t group;                   /* 1 or 4: the network's evaluation interval */
+    int32_t group;                   /* 1, 4, 8 or 16: the network's evaluation interval */
     float lr, beta1, beta2, eps;     /* Adam */
     int32_t objective;               /* 0: log M2; 1: cross entropy (see pyfpt_proposal_loss_grad) */
     float temper;                    /* beta in (0, 1] of pyfpt_proposal_loss_grad */

@@ -459,8 +459,8 @@ static int simulate_f32(const oracle_params *P, const consts_f32 *c, uint64_t t,
         drift_noise_f32(P, c, phi, &D, &S);
         float r;
         if (P->bias_kind == BIAS_MLP) {
-            /* evaluated at every step, or at the first step of each group of four */
-            if (P->eval_every == 1 || (k & 3u) == 0) r_mlp = (float)oracle_mlp_r(P, phi, (float)k * c->dN);
+            /* evaluated at the first step of each group of eval_every steps (1, 4, 8 or 16) */
+            if (k % (uint64_t)P->eval_every == 0) r_mlp = (float)oracle_mlp_r(P, phi, (float)k * c->dN);
             r = r_mlp;
         } else {
             r = bias_ratio_f32(P, c, phi, S);
@@ -503,7 +503,7 @@ static int simulate_f64(const oracle_params *P, uint64_t t, uint64_t *k_out, dou
         drift_noise_f64(P, phi, &D, &S);
         double r;
         if (P->bias_kind == BIAS_MLP) {
-            if (P->eval_every == 1 || (k & 3u) == 0) r_mlp = oracle_mlp_r(P, (float)phi, (float)((double)k * P->dN));
+            if (k % (uint64_t)P->eval_every == 0) r_mlp = oracle_mlp_r(P, (float)phi, (float)((double)k * P->dN));
             r = r_mlp;
         } else {
             r = bias_ratio_f64(P, phi, S);
@@ -622,7 +622,7 @@ typedef struct {
     float phi;      /* field at the evaluation point (before the step)       */
     uint32_t k;     /* step index of the evaluation point                    */
     float H;        /* sum over the group of eta = fma(r_0, dN, sqrt(dN) xi) */
-    uint32_t pn;    /* path index << 3 | steps in the group (1 .. 4)         */
+    uint32_t pn;    /* path index << 5 | steps in the group (1 .. 16)        */
 } oracle_record;
 
 /* Replay one path under the model's own proposal (binary32 mirror, identical to simulate_f32)
@@ -652,7 +652,7 @@ static int64_t records_f32(const oracle_params *P, const consts_f32 *c, uint64_t
         drift_noise_f32(P, c, phi, &D, &S);
         float r;
         if (P->bias_kind == BIAS_MLP) {
-            if (P->eval_every == 1 || (k & 3u) == 0) r_mlp = (float)oracle_mlp_r(P, phi, (float)k * c->dN);
+            if (k % (uint64_t)P->eval_every == 0) r_mlp = (float)oracle_mlp_r(P, phi, (float)k * c->dN);
             r = r_mlp;
         } else {
             r = bias_ratio_f32(P, c, phi, S);
@@ -681,7 +681,7 @@ static int64_t records_f32(const oracle_params *P, const consts_f32 *c, uint64_t
                     rec[n_rec].phi = phi_e;
                     rec[n_rec].k = k_e;
                     rec[n_rec].H = H;
-                    rec[n_rec].pn = (path << 3) | n_e;
+                    rec[n_rec].pn = (path << 5) | n_e;
                 }
                 n_rec += 1;
             }
@@ -769,7 +769,7 @@ void oracle_loss_grad(const oracle_params *P, const double *theta, const oracle_
         double x[3], h1[64], h2[64], s = 0.0;
         for (uint64_t e = rec_off[i]; e < rec_off[i + 1]; ++e) {
             const double r = net_f64(P, theta, rec[e].phi, rec[e].k, dN_f, x, h1, h2);
-            const double n = (double)(rec[e].pn & 7u);
+            const double n = (double)(rec[e].pn & 31u);
             s += (-r * (double)rec[e].H + r * r * n * dN * 0.5) * rec_weight;
         }
         lw_theta[i] = s;
@@ -798,7 +798,7 @@ void oracle_loss_grad(const oracle_params *P, const double *theta, const oracle_
         double x[3], h1[64], h2[64], d2[64];
         for (uint64_t e = rec_off[i]; e < rec_off[i + 1]; ++e) {
             const double r = net_f64(P, theta, rec[e].phi, rec[e].k, dN_f, x, h1, h2);
-            const double n = (double)(rec[e].pn & 7u);
+            const double n = (double)(rec[e].pn & 31u);
             const double go = ci * (r * n * dN - (double)rec[e].H) * osc * rec_weight;   /* d loss / d o */
             g[4480] += go;
             for (int u = 0; u < 64; ++u) {

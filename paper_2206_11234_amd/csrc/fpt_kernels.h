@@ -63,7 +63,7 @@ struct StepArgs {
     DumpDev dump;
     uint32_t chunk;
     const uint16_t *mlp_params;   // bfloat16 network shared by the batch (learned proposal)
-    int32_t mlp_every;            // evaluate the network every 1 or 4 steps
+    int32_t mlp_every;            // evaluate the network every 1, 4, 8 or 16 steps
 };
 
 // Per-instance merge metadata.

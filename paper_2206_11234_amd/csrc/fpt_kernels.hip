@@ -262,15 +262,23 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
                 }
             }
         } else {
-            // the network is evaluated by all 64 lanes together, outside divergent code
-            float r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
-            F4 z{};
-            if (active) z = normals4(k >> 2, t, stream, a.key0, a.key1);
-            const float zs[4] = {z.a, z.b, z.c, z.d};
+            // the network is evaluated by all 64 lanes together, outside divergent code.  One
+            // pass covers max(4, E) steps for the evaluation interval E (1, 4, 8 or 16): runs
+            // start at k = 0 and refill only between passes, so every lane of the wave is at a
+            // multiple of the pass length here and the evaluation points of all lanes coincide.
+            const int E = a.mlp_every;
+            const int n_q = E > 4 ? E >> 2 : 1;
+            float r_mlp = 0.0f;
+            for (int q = 0; q < n_q; ++q) {
+                if (q * 4 % E == 0) r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
+                F4 z{};
+                if (active && run) z = normals4(k >> 2, t, stream, a.key0, a.key1);
+                const float zs[4] = {z.a, z.b, z.c, z.d};
 #pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                if (s > 0 && a.mlp_every == 1) r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
-                if (active && run) step(zs[s], r_mlp);
+                for (int s = 0; s < 4; ++s) {
+                    if (s > 0 && E == 1) r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
+                    if (active && run) step(zs[s], r_mlp);
+                }
             }
         }
 

@@ -17,7 +17,7 @@ struct TrainRec {
     float phi;      // field before the group's first step
     uint32_t k;     // step index of the evaluation point
     float H;        // sum over the group of fma(r_0, dN, sqrt(dN) xi)
-    uint32_t pn;    // path index << 3 | steps in the group
+    uint32_t pn;    // path index << 5 | steps in the group (1 .. 16)
 };
 static_assert(sizeof(TrainRec) == 16, "record layout");
 
@@ -26,7 +26,7 @@ struct RecordArgs {
     const uint64_t *t_ids;      // run ids to replay
     uint32_t n_paths;
     uint32_t key0, key1;        // Philox key = seed of the sampling run
-    int32_t group;              // records per group of 1 or 4 steps
+    int32_t group;              // one record per group of 1, 4, 8 or 16 steps
     int32_t stride;             // keep the record of every stride-th group (g % stride == 0)
     int32_t mlp_every;
     const uint16_t *mlp_params; // bfloat16 network of the sampling proposal

@@ -59,39 +59,47 @@ __global__ __launch_bounds__(256) void fpt_record_kernel(RecordArgs a) {
     float H = 0.0f, phi_e = phi;
     uint32_t k_e = 0, n_e = 0;
     uint64_t n_rec = 0;
+    // the sampling network (if any) is evaluated every E steps, wave-wide: a pass covers
+    // max(4, E) steps, so every lane is at a multiple of the pass length at its start
+    const int E = (BIAS == BIAS_MLP) ? a.mlp_every : 4;
+    const int n_q = E > 4 ? E >> 2 : 1;
     while (__any(run)) {
         float r_mlp = 0.0f;
-        if constexpr (BIAS == BIAS_MLP) r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
-        F4 z{};
-        if (run) z = normals4(k >> 2, t, a.inst.stream, a.key0, a.key1);
-        const float zs[4] = {z.a, z.b, z.c, z.d};
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
+        for (int q = 0; q < n_q; ++q) {
             if constexpr (BIAS == BIAS_MLP) {
-                if (s > 0 && a.mlp_every == 1) r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
+                if (q * 4 % E == 0) r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
             }
-            if (run) {
-                if ((k & emask) == 0) {
-                    phi_e = phi;
-                    k_e = k;
-                    H = 0.0f;
-                    n_e = 0;
+            F4 z{};
+            if (run) z = normals4(k >> 2, t, a.inst.stream, a.key0, a.key1);
+            const float zs[4] = {z.a, z.b, z.c, z.d};
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                if constexpr (BIAS == BIAS_MLP) {
+                    if (s > 0 && E == 1) r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
                 }
-                float sxi;
-                const float r = em_step<POT, BIAS>(C, phi, k, lw, run, zs[s], r_mlp, sxi);
-                H = H + __builtin_fmaf(r, C.dN, sxi);
-                n_e += 1;
-                if ((k & emask) == 0 || !run) {
-                    const uint32_t grp = k_e / static_cast<uint32_t>(a.group);
-                    if (grp % static_cast<uint32_t>(a.stride) == 0 && n_rec < cap) {
-                        TrainRec R;
-                        R.phi = phi_e;
-                        R.k = k_e;
-                        R.H = H;
-                        R.pn = (i << 3) | n_e;
-                        a.rec[base + n_rec] = R;
+                if (run) {
+                    if ((k & emask) == 0) {
+                        phi_e = phi;
+                        k_e = k;
+                        H = 0.0f;
+                        n_e = 0;
                     }
-                    if (grp % static_cast<uint32_t>(a.stride) == 0) n_rec += 1;
+                    float sxi;
+                    const float r = em_step<POT, BIAS>(C, phi, k, lw, run, zs[s], r_mlp, sxi);
+                    H = H + __builtin_fmaf(r, C.dN, sxi);
+                    n_e += 1;
+                    if ((k & emask) == 0 || !run) {
+                        const uint32_t grp = k_e / static_cast<uint32_t>(a.group);
+                        if (grp % static_cast<uint32_t>(a.stride) == 0 && n_rec < cap) {
+                            TrainRec R;
+                            R.phi = phi_e;
+                            R.k = k_e;
+                            R.H = H;
+                            R.pn = (i << 5) | n_e;
+                            a.rec[base + n_rec] = R;
+                        }
+                        if (grp % static_cast<uint32_t>(a.stride) == 0) n_rec += 1;
+                    }
                 }
             }
         }
@@ -163,7 +171,7 @@ __global__ __launch_bounds__(256) void fpt_train_fwd_kernel(TrainArgs a, const f
         for (int u = 0; u < 64; ++u) o = __builtin_fmaf(th[NET_W3 + u], net_unit2(th, u, h1), o);
         const float r = a.mc.out_scale * (o + th0[NET_B3]);
         const double rd = static_cast<double>(r);
-        const double n = static_cast<double>(R.pn & 7u);
+        const double n = static_cast<double>(R.pn & 31u);
         s += (-rd * static_cast<double>(R.H) + rd * rd * n * hdN) * static_cast<double>(a.rec_weight);
     }
     red[threadIdx.x] = s;
@@ -267,8 +275,8 @@ __global__ __launch_bounds__(64) void fpt_train_bwd_kernel(TrainArgs a, const fl
             }
             if (valid) {
                 const double r = static_cast<double>(a.mc.out_scale * (o + th[NET_B3]));
-                const uint32_t path = R.pn >> 3;
-                const double n = static_cast<double>(R.pn & 7u);
+                const uint32_t path = R.pn >> 5;
+                const double n = static_cast<double>(R.pn & 31u);
                 g = static_cast<float>(a.c[path] * (r * n * dNd - static_cast<double>(R.H)) *
                                        static_cast<double>(a.mc.out_scale) * static_cast<double>(a.rec_weight));
             }

@@ -170,7 +170,8 @@ int validate(const pyfpt_instance &I, int i) {
         const pyfpt_mlp &M = B.mlp;
         if (!M.params) return fail(PYFPT_EINVAL, "instance %d: learned bias needs device parameters", i);
         if (M.hidden != 64) return fail(PYFPT_EINVAL, "instance %d: learned bias supports hidden = 64 only", i);
-        if (M.eval_every != 1 && M.eval_every != 4) return fail(PYFPT_EINVAL, "instance %d: eval_every must be 1 or 4", i);
+        if (M.eval_every != 1 && M.eval_every != 4 && M.eval_every != 8 && M.eval_every != 16)
+            return fail(PYFPT_EINVAL, "instance %d: eval_every must be 1, 4, 8 or 16", i);
         bool ok = std::isfinite(M.out_scale) && std::isfinite(B.target_N);
         for (int q = 0; q < 3; ++q) ok = ok && std::isfinite(M.in_mean[q]) && std::isfinite(M.in_inv_scale[q]);
         if (!ok) return fail(PYFPT_EINVAL, "instance %d: learned bias constants must be finite", i);
@@ -918,9 +919,9 @@ int pyfpt_proposal_records(const pyfpt_instance *inst, uint64_t seed, const uint
                            uint32_t *k_out, double *lw_out, int32_t *status_out, const pyfpt_options *opt) {
     if (!inst || n_paths < 0 || (n_paths > 0 && (!t_ids || !rec_off || !k_out || !lw_out || !status_out)))
         return fail(PYFPT_EINVAL, "NULL argument or n_paths < 0");
-    if (group != 1 && group != 4) return fail(PYFPT_EINVAL, "group must be 1 or 4");
+    if (group != 1 && group != 4 && group != 8 && group != 16) return fail(PYFPT_EINVAL, "group must be 1, 4, 8 or 16");
     if (stride < 1) return fail(PYFPT_EINVAL, "stride must be >= 1");
-    if (n_paths >= (1 << 29)) return fail(PYFPT_EINVAL, "n_paths must be < 2^29");
+    if (n_paths >= (1 << 27)) return fail(PYFPT_EINVAL, "n_paths must be < 2^27");
     Prepared P;
     int rc = prepare(inst, 1, P);
     if (rc) return rc;
@@ -955,7 +956,7 @@ int pyfpt_proposal_loss_grad(const pyfpt_mlp *net, double target_N, double dN, c
                              const pyfpt_options *opt) {
     if (!net || !theta || !rec_off || !lw0 || !loss || !grad || !lw_theta || (n_rec > 0 && !rec))
         return fail(PYFPT_EINVAL, "NULL argument");
-    if (n_paths < 1 || n_paths >= (1 << 29)) return fail(PYFPT_EINVAL, "n_paths must be 1 .. 2^29-1");
+    if (n_paths < 1 || n_paths >= (1 << 27)) return fail(PYFPT_EINVAL, "n_paths must be 1 .. 2^27-1");
     if (objective != 0 && objective != 1) return fail(PYFPT_EINVAL, "objective must be 0 or 1");
     if (!(temper > 0.0 && temper <= 1.0)) return fail(PYFPT_EINVAL, "temper must be in (0, 1]");
     if (!(rec_weight >= 1.0) || !std::isfinite(rec_weight) || (objective == 0 && rec_weight != 1.0))
@@ -966,7 +967,7 @@ int pyfpt_proposal_loss_grad(const pyfpt_mlp *net, double target_N, double dN, c
     if (rc) return rc;
     for (uint64_t e = 0; e < n_rec; ++e) {
         const uint32_t pn = rec[e].path_n;
-        if ((pn >> 3) >= static_cast<uint32_t>(n_paths) || (pn & 7u) < 1 || (pn & 7u) > 4)
+        if ((pn >> 5) >= static_cast<uint32_t>(n_paths) || (pn & 31u) < 1 || (pn & 31u) > 16)
             return fail(PYFPT_EINVAL, "record %llu: path index or step count out of range",
                         static_cast<unsigned long long>(e));
     }
@@ -1014,9 +1015,10 @@ int pyfpt_train_proposal(const pyfpt_instance *inst, uint64_t seed, const pyfpt_
                          uint16_t *params_bf16, pyfpt_train_report *report, const pyfpt_options *opt) {
     if (!inst || !cfg || !theta || !params_bf16 || !report) return fail(PYFPT_EINVAL, "NULL argument");
     if (inst->bias.kind != PYFPT_BIAS_MLP) return fail(PYFPT_EINVAL, "the instance's bias must be the learned bias");
-    if (cfg->group != 1 && cfg->group != 4) return fail(PYFPT_EINVAL, "group must be 1 or 4");
-    if (cfg->rounds < 1 || cfg->steps < 1 || cfg->n_sample < 1 || cfg->max_paths < 0)
-        return fail(PYFPT_EINVAL, "need rounds >= 1, steps >= 1, n_sample >= 1, max_paths >= 0");
+    if (cfg->group != 1 && cfg->group != 4 && cfg->group != 8 && cfg->group != 16)
+        return fail(PYFPT_EINVAL, "group must be 1, 4, 8 or 16");
+    if (cfg->rounds < 1 || cfg->steps < 1 || cfg->n_sample < 1 || cfg->max_paths < 0 || cfg->max_paths >= (1 << 27))
+        return fail(PYFPT_EINVAL, "need rounds >= 1, steps >= 1, n_sample >= 1, 0 <= max_paths < 2^27");
     if (!(cfg->window_hi > cfg->window_lo) || !std::isfinite(cfg->window_lo) || !std::isfinite(cfg->window_hi))
         return fail(PYFPT_EINVAL, "need a finite window lo < hi");
     if (!(cfg->lr > 0) || !(cfg->beta1 >= 0 && cfg->beta1 < 1) || !(cfg->beta2 >= 0 && cfg->beta2 < 1) || !(cfg->eps > 0))
@@ -1097,7 +1099,10 @@ int pyfpt_train_proposal(const pyfpt_instance *inst, uint64_t seed, const pyfpt_
             const double N = static_cast<double>(hk[t]) * I.dN;
             if (N > cfg->window_lo && N <= cfg->window_hi) {
                 R.n_window += 1;
-                if (cfg->max_paths == 0 || static_cast<int32_t>(ids.size()) < cfg->max_paths) {
+                // records carry the path index in 27 bits
+                const bool room = cfg->max_paths == 0 ? ids.size() < (1u << 27) - 1u
+                                                      : static_cast<int32_t>(ids.size()) < cfg->max_paths;
+                if (room) {
                     ids.push_back(t);
                     lw0.push_back(hlw[t]);
                     mx = std::max(mx, hlw[t]);

@@ -125,13 +125,16 @@ def test_training_and_combine_entry_points_reject_bad_input(lib):
     grad = np.zeros(4481)
     lwt = np.zeros(2)
     off2 = np.array([0, 1, 3], np.uint64)
-    rec["pn"] = [(0 << 3) | 4, (1 << 3) | 4, (5 << 3) | 4]       # path index 5 >= n_paths
+    rec["pn"] = [(0 << 5) | 4, (1 << 5) | 4, (5 << 5) | 4]       # path index 5 >= n_paths
     assert L.pyfpt_proposal_loss_grad(ctypes.byref(net), 196.0, 1e-3, vp(theta), vp(rec), 3, vp(off2), 2, vp(lw), 10.0,
                                       0, 1.0, 1.0, vp(loss), vp(grad), vp(lwt), ctypes.byref(opt)) == lib.PYFPT_EINVAL
-    rec["pn"] = [(0 << 3) | 4, (1 << 3) | 0, (1 << 3) | 4]       # zero steps in a group
+    rec["pn"] = [(0 << 5) | 4, (1 << 5) | 0, (1 << 5) | 4]       # zero steps in a group
     assert L.pyfpt_proposal_loss_grad(ctypes.byref(net), 196.0, 1e-3, vp(theta), vp(rec), 3, vp(off2), 2, vp(lw), 10.0,
                                       0, 1.0, 1.0, vp(loss), vp(grad), vp(lwt), ctypes.byref(opt)) == lib.PYFPT_EINVAL
-    rec["pn"] = [(0 << 3) | 4, (1 << 3) | 4, (1 << 3) | 4]
+    rec["pn"] = [(0 << 5) | 4, (1 << 5) | 17, (1 << 5) | 4]      # more steps than the largest group
+    assert L.pyfpt_proposal_loss_grad(ctypes.byref(net), 196.0, 1e-3, vp(theta), vp(rec), 3, vp(off2), 2, vp(lw), 10.0,
+                                      0, 1.0, 1.0, vp(loss), vp(grad), vp(lwt), ctypes.byref(opt)) == lib.PYFPT_EINVAL
+    rec["pn"] = [(0 << 5) | 4, (1 << 5) | 4, (1 << 5) | 4]
     assert L.pyfpt_proposal_loss_grad(ctypes.byref(net), 196.0, 1e-3, vp(theta), vp(rec), 3, vp(off2), 2, vp(lw), 10.0,
                                       2, 1.0, 1.0, vp(loss), vp(grad), vp(lwt), ctypes.byref(opt)) == lib.PYFPT_EINVAL  # objective
     assert L.pyfpt_proposal_loss_grad(ctypes.byref(net), 196.0, 1e-3, vp(theta), vp(rec), 3, vp(off2), 2, vp(lw), 10.0,

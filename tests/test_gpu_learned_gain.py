@@ -5,7 +5,7 @@ The window (190, 202] lies near P ~ 1e-30.  With B = A S the weights of the runs
 it spread over many decades (Sec. 3.1 notes this limit of a fixed bias), so a fixed A
 resolves it with a handful of effective samples.  A network trained with the cross-entropy
 objective (window weights w_0^(1/2)) through windows at N = 60, 100, 140 and 196, 8000 window
-runs per round, must (i) estimate P in the window in
+runs per round, evaluated once per 16 steps, must (i) estimate P in the window in
 agreement with the pole expansion (Sturm-Liouville solve of the oracle, end moved by
 beta S sqrt(dN) for the discrete monitoring) and (ii) reach a much larger effective sample
 size in the window than the best fixed bias from the same number of runs.
@@ -48,7 +48,7 @@ def test_learned_proposal_resolves_the_far_tail(fpt):
     v[:4480] = np.random.default_rng(0).normal(0.0, 1e-2, 4480)
     v[4480] = 1.0
     p0 = W.MlpParams(W.bf16_round(v), in_mean=(5.0, target, target), in_inv_scale=(0.4, 0.005, 0.01),
-                     out_scale=1.0, eval_every=4)
+                     out_scale=1.0, eval_every=16)
     inst = dataclasses.replace(W.c4_instance(p0, n_traj=200_000, target_N=target, stream=base.stream), edges=edges)
     theta = p0.values_f32()
     for si, c in enumerate((60.0, 100.0, 140.0, 196.0)):

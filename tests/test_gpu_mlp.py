@@ -45,7 +45,7 @@ def test_mlp_forward_matches_oracle(fpt, seed, scale):
     assert np.median(err) < 2e-4 * params.out_scale
 
 
-@pytest.mark.parametrize("every", [4, 1])
+@pytest.mark.parametrize("every", [4, 1, 8, 16])
 def test_mlp_sampler_matches_oracle(fpt, every):
     params = W.c4_params(3, out_scale=1.0, eval_every=every)
     inst = W.c4_instance(params, n_traj=600)
@@ -66,7 +66,7 @@ def test_mlp_sampler_matches_oracle(fpt, every):
     assert int(res.count.sum()) == inst.n_traj
 
 
-@pytest.mark.parametrize("every", [4, 1])
+@pytest.mark.parametrize("every", [4, 1, 8, 16])
 def test_constant_network_sampler_bit_exact(fpt, every):
     """A network whose only nonzero parameter is b3 gives r = out_scale b3 exactly on the matrix
     cores (zero weights times bounded activations add exact zeros), so the learned path must

@@ -43,13 +43,14 @@ def _const_net(r0, every=4):
     return W.MlpParams(v, out_scale=2.0 * r0, eval_every=every)
 
 
-@pytest.mark.parametrize("proposal", ["fixed", "constant_network"])
-def test_records_bit_exact(fpt, proposal):
+@pytest.mark.parametrize("proposal,group", [("fixed", 4), ("constant_network", 4), ("fixed", 16),
+                                            ("constant_network", 16)])
+def test_records_bit_exact(fpt, proposal, group):
     base = W.c2(3000)[3]                       # m = 1, phi_in = 6, wall 8, A = 1
-    inst = base if proposal == "fixed" else W.c4_instance(_const_net(1.0), n_traj=3000, stream=base.stream)
+    inst = base if proposal == "fixed" else W.c4_instance(_const_net(1.0, group), n_traj=3000, stream=base.stream)
     ids, k, lw = _pick(fpt, inst, 6000, 60000, 48)
-    g = fpt.proposal_records(inst, 0, ids, k, 4)
-    o = O.records(to_model(inst), 0, ids, 4)
+    g = fpt.proposal_records(inst, 0, ids, k, group)
+    o = O.records(to_model(inst), 0, ids, group)
     print(f"{proposal}: {len(ids)} paths, {g.rec.size} records")
     assert np.array_equal(g.k, o.k) and np.array_equal(g.k, k)
     assert np.array_equal(g.lw, o.lw) and np.array_equal(g.lw, lw)
@@ -58,24 +59,26 @@ def test_records_bit_exact(fpt, proposal):
     assert g.rec.tobytes() == o.rec.tobytes()
 
 
-def test_records_learned_proposal_mostly_identical(fpt):
-    params = W.c4_params(3, out_scale=1.0)
+@pytest.mark.parametrize("every", [4, 16])
+def test_records_learned_proposal_mostly_identical(fpt, every):
+    params = W.c4_params(3, out_scale=1.0, eval_every=every)
     inst = W.c4_instance(params, n_traj=3000)
     ids, k, lw = _pick(fpt, inst, 2000, 200000, 64)
-    g = fpt.proposal_records(inst, 0, ids, k, 4)
+    g = fpt.proposal_records(inst, 0, ids, k, every)
     assert np.array_equal(g.k, k) and np.array_equal(g.lw, lw)      # the replay is the sampled run
-    o = O.records(to_model(inst), 0, ids, 4)
+    o = O.records(to_model(inst), 0, ids, every)
     same = o.k == g.k
     print(f"learned proposal: identical step counts {same.mean():.3f}")
     assert same.mean() > 0.9
 
 
-@pytest.mark.parametrize("objective,temper,stride", [(0, 1.0, 1), (1, 1.0, 1), (1, 0.5, 1), (1, 0.5, 4)])
-def test_loss_and_gradient_match_oracle(fpt, objective, temper, stride):
+@pytest.mark.parametrize("objective,temper,stride,group", [(0, 1.0, 1, 4), (1, 1.0, 1, 4), (1, 0.5, 1, 4),
+                                                           (1, 0.5, 4, 4), (1, 0.5, 1, 16)])
+def test_loss_and_gradient_match_oracle(fpt, objective, temper, stride, group):
     base = W.c2(3000)[3]
     ids, k, lw = _pick(fpt, base, 6000, 60000, 40)
-    g = fpt.proposal_records(base, 0, ids, k, 4, stride)
-    o = O.records(to_model(base), 0, ids, 4, stride)
+    g = fpt.proposal_records(base, 0, ids, k, group, stride)
+    o = O.records(to_model(base), 0, ids, group, stride)
     assert g.rec.tobytes() == o.rec.tobytes()
     p = W.c4_params(7, scale=1.5, out_scale=0.8)
     theta = p.values_f32()

@@ -81,7 +81,7 @@ def test_single_paths_through_N_and_target_with_biases():
         assert np.max(np.abs(r - want)) <= 1e-6, target
 
 
-@pytest.mark.parametrize("every", [1, 4])
+@pytest.mark.parametrize("every", [1, 4, 8, 16])
 def test_constant_network_sampler_equals_noise_scaled_bias(every):
     base = W.c2(96)[3]                          # m = 1, phi_in = 6, wall at 8, A = 1
     m_fixed = O.Model.from_instance(base)

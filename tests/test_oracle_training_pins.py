@@ -25,21 +25,23 @@ def _short_paths(model, lo, hi, n_want, seed=0, pool=4000):
     return ids.astype(np.uint64), tr
 
 
-def test_replay_reproduces_sampler_runs():
+@pytest.mark.parametrize("E", [4, 16])
+def test_replay_reproduces_sampler_runs(E):
     m = _fixed_model()
     ids, tr = _short_paths(m, 6000, 40000, 12)
-    rec = O.records(m, 0, ids, 4)
+    rec = O.records(m, 0, ids, E)
     assert np.array_equal(rec.k, tr.k[ids]) and np.array_equal(rec.status, tr.status[ids])
     assert np.array_equal(rec.lw, tr.lw[ids])
     n = np.diff(rec.off.astype(np.int64))
-    assert np.array_equal(n, (rec.k.astype(np.int64) + 3) // 4)
-    # the last record of each path holds the remainder of its steps; all others hold 4
-    ln = rec.rec["pn"] & 7
+    assert np.array_equal(n, (rec.k.astype(np.int64) + E - 1) // E)
+    # the last record of each path holds the remainder of its steps; all others hold E
+    ln = rec.rec["pn"] & 31
+    assert np.array_equal(rec.rec["pn"] >> 5, np.repeat(np.arange(len(ids)), n))
     last = rec.off[1:].astype(np.int64) - 1
-    assert np.all(ln[last] == (rec.k - 1) % 4 + 1)
+    assert np.all(ln[last] == (rec.k - 1) % E + 1)
     mask = np.ones(len(ln), bool)
     mask[last] = False
-    assert np.all(ln[mask] == 4)
+    assert np.all(ln[mask] == E)
     assert np.all(rec.rec["k"][rec.off[:-1].astype(np.int64)] == 0)
 
 
