@@ -360,6 +360,71 @@ def sl_modes(model: Model, n_modes: int = 3, lam_max: float | None = None, n_sca
 
 
 # --------------------------------------------------------------------------
+# The zero-variance proposal for a window of first-passage times.
+#
+# For the event N in (lo, hi], the proposal with zero weight variance is the target process
+# conditioned on that event (a Doob h-transform): its drift is D + S^2 d/dphi ln h(phi, n) with
+# h(phi, n) = P(N in (lo, hi] | field phi at time n).  From the pole expansion of the
+# first-passage density from phi, p(s | phi) = sum_n Lambda_n c_n psi_n(phi) exp(-Lambda_n s)
+# (App. A; psi_n(phi_end) = 0, psi_n'(phi_UV) = 0, c_n = <psi_n, 1>_rho / <psi_n, psi_n>_rho),
+#   h(phi, n) = sum_n c_n psi_n(phi) [exp(-Lambda_n (lo - n)) - exp(-Lambda_n (hi - n))]
+# for n <= lo, and the optimal bias in noise units is r*(phi, n) = S(phi) d/dphi ln h(phi, n).
+# Far from the window only the slowest mode survives and r* tends to the quasi-stationary drift
+# S psi_0'/psi_0, independent of n.  The truncated sum needs lo - n well above 1/Lambda_1.
+# --------------------------------------------------------------------------
+@dataclass
+class WindowBias:
+    lam: np.ndarray     # Lambda_n
+    c: np.ndarray       # c_n
+    sols: list          # dense shooting solutions (psi_n, psi_n') on [phi_end, phi_UV]
+    lo: float
+    hi: float
+    s2: object          # phi -> S^2 of the target process
+
+    def _terms(self, n):
+        n = np.asarray(n, dtype=np.float64)
+        return [ck * (np.exp(-lk * (self.lo - n)) - np.exp(-lk * (self.hi - n))) for lk, ck in zip(self.lam, self.c)]
+
+    def h(self, phi, n):
+        """Probability of ending in (lo, hi] from phi at time n (n <= lo)."""
+        phi = np.asarray(phi, dtype=np.float64)
+        return sum(t * sol.sol(phi)[0] for t, sol in zip(self._terms(n), self.sols))
+
+    def r(self, phi, n):
+        """The zero-variance bias in noise units, S d/dphi ln h."""
+        phi = np.asarray(phi, dtype=np.float64)
+        terms = self._terms(n)
+        h = sum(t * sol.sol(phi)[0] for t, sol in zip(terms, self.sols))
+        dh = sum(t * sol.sol(phi)[1] for t, sol in zip(terms, self.sols))
+        S = np.sqrt(np.vectorize(lambda x: self.s2(x)[1])(phi))
+        return S * dh / h
+
+    def conditioned_density(self, phi):
+        """Density of the field long before the window under the conditioned process:
+        rho psi_0^2 (rho = (2/S^2) e^Psi, the weight that makes the generator self-adjoint),
+        normalised by the trapezoid rule over the given ascending grid."""
+        phi = np.asarray(phi, dtype=np.float64)
+        y = self.sols[0].sol(phi)
+        s2 = np.vectorize(lambda x: self.s2(x)[1])(phi)
+        q = 2.0 / s2 * np.exp(y[2]) * y[0] ** 2
+        return q / np.trapezoid(q, phi)
+
+
+def window_bias(model: Model, lo: float, hi: float, n_modes: int = 6, lam_max: float | None = None,
+                n_scan: int = 200) -> WindowBias:
+    """The zero-variance bias r*(phi, n) for first passage in (lo, hi] (finite reflecting wall)."""
+    if not np.isfinite(model.phi_uv):
+        raise ValueError("the pole expansion needs a finite reflecting wall")
+    modes = sl_modes(model, n_modes, lam_max=lam_max, n_scan=n_scan)
+    sols, cs = [], []
+    for lam in modes.lam:
+        sol = _shoot(model, lam, dense=True)
+        sols.append(sol)
+        cs.append(sol.y[3, -1] / sol.y[4, -1])
+    return WindowBias(modes.lam, np.array(cs), sols, float(lo), float(hi), _scalar_drift_s2(model))
+
+
+# --------------------------------------------------------------------------
 # Cumulants of N and the Edgeworth expansion (App. B).
 #
 # The cumulant generating function K(s, phi) = ln E[exp(s N)] of the first-passage time from

@@ -78,3 +78,21 @@ def test_learned_proposal_resolves_the_far_tail(fpt):
           f"Kish rel err {rel:.3f}); fixed A = 0.8, 1.0: ESS {ess_f[0]:.1f}, {ess_f[1]:.1f}")
     assert abs(p_l / p_ref - 1.0) < 4 * rel + 0.05
     assert ess_l > 10 * max(ess_f)
+    # the ceiling: the zero-variance bias for the window (the process conditioned on ending in
+    # it, from the pole expansion).  Long before the window it is the quasi-stationary drift;
+    # weighted by where the conditioned runs spend that time, the trained network must be closer
+    # to it than the best constant bias (the fixed noise-scaled family) can be.
+    wb = R.window_bias(shifted, lo, hi, n_modes=6, lam_max=4.0, n_scan=160)
+    x = np.linspace(shifted.phi_end + 0.02, shifted.phi_uv, 300)
+    q = wb.conditioned_density(x)
+    d_l, d_c = [], []
+    for n in (40.0, 80.0, 120.0, 160.0):
+        r_star = wb.r(x, n)
+        r_net = fpt.mlp_forward(learned.mlp, target, x.astype(np.float32), np.full(x.size, n, np.float32))
+        mean = np.trapezoid(q * r_star, x)
+        d_l.append(np.trapezoid(q * (r_net - r_star) ** 2, x))
+        d_c.append(np.trapezoid(q * (mean - r_star) ** 2, x))
+        print(f"N = {n:g}: weighted rms |r_net - r*| {math.sqrt(d_l[-1]):.3f}, best constant {math.sqrt(d_c[-1]):.3f}, "
+              f"r* at phi = 6, 7, 7.8: {np.round(wb.r(np.array([6.0, 7.0, 7.8]), n), 3)}, "
+              f"net {np.round(fpt.mlp_forward(learned.mlp, target, np.array([6, 7, 7.8], np.float32), np.full(3, n, np.float32)), 3)}")
+    assert sum(d_l) < sum(d_c)
