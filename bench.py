@@ -77,6 +77,8 @@ def parse():
     p.add_argument("--c5-total", type=int, default=1_000_000_000)
     p.add_argument("--c5-launches", type=int, default=7, help="launches the amplitudes are split over")
     p.add_argument("--c5-save", type=str, default="", help="write the per-amplitude result tables to this .npz")
+    p.add_argument("--mlp-sampler", action="store_true",
+                   help="time the learned-bias sampler alone (untrained network, r ~ 1) on the diffusion case")
     p.add_argument("--c3", action="store_true",
                    help="the 64-instance batched sweep in one graph-replayed launch with the autotuned shape")
     p.add_argument("--copy-calibration", action="store_true",
@@ -249,7 +251,7 @@ def learned_gain(args):
     train_s = time.perf_counter() - t0
     p1 = W.MlpParams(theta, in_mean=p0.in_mean, in_inv_scale=p0.in_inv_scale, out_scale=1.0,
                      eval_every=args.eval_every)
-    learned = evaluate(dataclasses.replace(inst0, mlp=p1), "learned", block=256, wg_per_cu=1, chunk=1)
+    learned = evaluate(dataclasses.replace(inst0, mlp=p1), "learned", block=256, wg_per_cu=2, chunk=1)
     # a fixed bias is a candidate only where its window estimate is trusted by the paper's
     # n_j > 400 criterion (Sec. 2.1); with fewer runs its error estimate is itself unreliable
     cands = [f for f in out["fixed"] if f["gpu_s_to_1pct"] and f["count"] > 400]
@@ -258,6 +260,41 @@ def learned_gain(args):
     out.update(learned=learned, train_s=train_s, train_rounds=rep, best_fixed=best["label"] if best else None,
                gain=(best["gpu_s_to_1pct"] / lg) if (best and lg) else None,
                gain_with_training=(best["gpu_s_to_1pct"] / (lg + train_s)) if (best and lg) else None)
+    print(json.dumps(out), flush=True)
+
+
+def mlp_sampler_run(args):
+    """The learned-bias step kernel alone: the diffusion-dominated quadratic case (m = 1,
+    phi_in = 6, wall at 8, dN = 1e-3) under the untrained network (r ~ 1: small random weights,
+    output bias 1), args.n_eval runs, network evaluated every args.eval_every steps."""
+    import dataclasses
+    import numpy as np
+    import torch
+    import paper_2206_11234_amd as F
+    import workloads as W
+
+    torch.cuda.set_device(0)
+    base = W.c2(args.n_eval)[3]
+    v = np.zeros(W.MlpParams.N_PARAMS, np.float32)
+    v[:4480] = np.random.default_rng(0).normal(0.0, 1e-2, 4480)
+    v[4480] = 1.0
+    p0 = W.MlpParams(W.bf16_round(v), in_mean=(5.0, args.target, args.target), in_inv_scale=(0.4, 0.005, 0.01),
+                     out_scale=1.0, eval_every=args.eval_every)
+    inst = dataclasses.replace(W.c4_instance(p0, n_traj=args.n_eval, target_N=args.target, stream=base.stream),
+                               edges=np.linspace(0.0, 400.0, 201))
+    F.run(dataclasses.replace(inst, n_traj=20000), 2, block=256, wg_per_cu=2, chunk=1)   # warm-up
+    kms, steps = [], 0
+    for s in range(args.steps):
+        res, _, tm = F.run(inst, 2, block=256, wg_per_cu=2, chunk=1, timing=True)
+        kms.append(tm[0])
+        steps = res.total_steps
+        print(f"[mlp] pass {s}: {tm[0]:.1f} ms", file=sys.stderr, flush=True)
+    k = sum(kms) / len(kms) / 1e3
+    flop = 34 * 32 * 32 * 16 * 2 / 64 / args.eval_every      # matrix-core flop per trajectory-step
+    out = {"workload": f"learned-bias sampler, diffusion case, {args.n_eval} runs, network every {args.eval_every} steps",
+           "kernel": "fpt_step_mlp1_kernel", "kernel_ms": k * 1e3, "steps": steps, "traj_steps_per_s": steps / k,
+           "mfma_flop_per_step": flop, "mfma_pflops": steps / k * flop / 1e15,
+           "mfma_frac_bf16_peak": steps / k * flop / 2.5e15}
     print(json.dumps(out), flush=True)
 
 
@@ -316,6 +353,9 @@ def main():
         return
     if args.c3:
         c3_run(args)
+        return
+    if args.mlp_sampler:
+        mlp_sampler_run(args)
         return
     import numpy as np
     import torch
