@@ -124,7 +124,12 @@ typedef struct pyfpt_instance {
     double phi_uv;                   /* reflecting wall; +INFINITY = none; phi_uv >= phi_in */
     double phi_esc;                  /* escape level without a wall; 0 -> 100 phi_in */
     double dN;                       /* step, > 0 */
-    uint64_t n_traj;                 /* runs t = 0 .. n_traj-1 */
+    uint64_t n_traj;                 /* runs t = t_first .. t_first + n_traj - 1 */
+    uint64_t t_first;                /* first run id (0 usually).  Runs are addressed by their id
+                                        alone, so id ranges split one instance into shards (other
+                                        launches or devices) whose counts and jackknife tables add
+                                        and whose log-sum-exp sums combine; t_first + n_traj must
+                                        not exceed 2^64 - 1 */
     uint64_t k_max;                  /* step cap, 1 .. 2^32-1; 0 -> 2^20 */
     uint32_t stream;                 /* noise stream id (Philox counter word 3) */
     uint32_t reserved;
@@ -209,6 +214,7 @@ typedef struct pyfpt_options {
     double phi_esc;                  /* pyfpt_run only: escape level (0 -> 100 phi_in) */
     uint32_t stream_id;              /* pyfpt_run only: noise stream */
     uint32_t reserved;
+    uint64_t t_first;                /* pyfpt_run only: first run id (see pyfpt_instance) */
     float *timing_ms;                /* if not NULL: [0] step kernel, [1] merge kernel (synchronises) */
 } pyfpt_options;
 

@@ -42,7 +42,7 @@ class pyfpt_instance(ctypes.Structure):
     _fields_ = [("pot", pyfpt_potential), ("bias", pyfpt_bias),
                 ("phi_in", ctypes.c_double), ("phi_end", ctypes.c_double), ("phi_uv", ctypes.c_double),
                 ("phi_esc", ctypes.c_double), ("dN", ctypes.c_double),
-                ("n_traj", ctypes.c_uint64), ("k_max", ctypes.c_uint64),
+                ("n_traj", ctypes.c_uint64), ("t_first", ctypes.c_uint64), ("k_max", ctypes.c_uint64),
                 ("stream", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
                 ("cost_hint", ctypes.c_double), ("bins", pyfpt_bins)]
 
@@ -69,7 +69,7 @@ class pyfpt_options(ctypes.Structure):
                 ("wg_per_cu", ctypes.c_int32), ("use_graph", ctypes.c_int32),
                 ("workspace", ctypes.c_void_p), ("workspace_bytes", ctypes.c_size_t),
                 ("dump", pyfpt_dump), ("k_max", ctypes.c_uint64), ("phi_esc", ctypes.c_double),
-                ("stream_id", ctypes.c_uint32), ("reserved", ctypes.c_uint32),
+                ("stream_id", ctypes.c_uint32), ("reserved", ctypes.c_uint32), ("t_first", ctypes.c_uint64),
                 ("timing_ms", ctypes.POINTER(ctypes.c_float))]
 
 

@@ -214,6 +214,7 @@ def make_instance(inst, n_sub: int, keep: list) -> L.pyfpt_instance:
     I.phi_esc = float(_f(inst, "phi_esc", 0.0))
     I.dN = float(inst.dN)
     I.n_traj = int(inst.n_traj)
+    I.t_first = int(_f(inst, "t_first", 0))
     I.k_max = int(_f(inst, "k_max", 0))
     I.stream = int(_f(inst, "stream", 0))
     I.cost_hint = float(_f(inst, "cost_hint", 0.0))
@@ -299,6 +300,7 @@ def run_single_abi(inst, seed: int = 0, *, n_sub: int = 16, block: int = 512, ch
     opt.k_max = I.k_max
     opt.phi_esc = I.phi_esc
     opt.stream_id = I.stream
+    opt.t_first = I.t_first
     L.check(lib.pyfpt_run(ctypes.byref(I.pot), I.phi_in, I.phi_end, I.phi_uv, I.dN, ctypes.byref(I.bias), I.n_traj,
                           int(seed), ctypes.byref(I.bins), ctypes.byref(res), ctypes.byref(opt)))
     return Result(np.asarray(inst.edges, np.float64), n_sub, counts, values, lay)

@@ -21,6 +21,7 @@ struct InstDev {
     uint32_t k_center;    // expected step count: centre of k in the correlation sums
     uint64_t n_traj;
     uint64_t v_begin;     // first id of this instance in the shared queue
+    uint64_t t_first;     // run id of the instance's first run
 };
 
 // Per-workgroup table: byte offsets inside one workgroup's slice.
@@ -71,6 +72,7 @@ struct MergeInst {
     uint32_t row_base, n_rows, n_bins, edge_base;
     uint64_t counts_off, values_off;  // into the staging result arrays
     uint64_t n_traj;
+    uint64_t t_first;                 // runs t_first .. t_first + n_traj - 1 (jackknife subset t mod J)
 };
 
 struct MergeArgs {

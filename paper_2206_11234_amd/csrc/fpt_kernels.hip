@@ -152,6 +152,7 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
     // lane state
     StepConsts C{};
     uint32_t stream = 0, n_bins = 0, row_base = 0, thr_base = 0, dump_slot = 0, k_center = 0;
+    uint64_t t0 = 0;            // the current instance's first run id
     int cur_inst = -1;
     float phi = 0.0f;
     uint32_t k = 0;
@@ -180,6 +181,7 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
         thr_base = I.thr_base;
         dump_slot = I.dump_slot;
         k_center = I.k_center;
+        t0 = I.t_first;
         if constexpr (BIAS == BIAS_MLP) mc = I.mlp;
         cur_inst = single_inst;
     }
@@ -230,9 +232,11 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
                         thr_base = I.thr_base;
                         dump_slot = I.dump_slot;
                         k_center = I.k_center;
+                        t0 = I.t_first;
                         if constexpr (BIAS == BIAS_MLP) mc = I.mlp;
                         cur_inst = ii;
                     }
+                    t += t0;                   // the run's id: Philox counter and jackknife subset
                     if (acc.inst != ii) {
                         if (acc.inst >= 0) acc_commit_direct(T, acc);
                         acc_reset(acc, ii);
@@ -336,8 +340,8 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
             acc.wk2 = lse2(acc.wk2, lw + 2.0 * lk);
             acc.k2 += kd * kd;
             acc.steps += kd;
-            if (a.dump.n != 0 && (t % a.dump.stride) == 0) {
-                const uint64_t idx = t / a.dump.stride;
+            if (a.dump.n != 0 && ((t - t0) % a.dump.stride) == 0) {
+                const uint64_t idx = (t - t0) / a.dump.stride;
                 if (idx < a.dump.n) {
                     const uint64_t pos = static_cast<uint64_t>(dump_slot) * a.dump.n + idx;
                     a.dump.k[pos] = k;
@@ -591,7 +595,10 @@ __global__ __launch_bounds__(256) void fpt_finalize_kernel(MergeArgs a) {
         // jackknife: P_s / P = exp(lse_s - lse) * n_traj / n_s; spread over subsets / sqrt(J)
         double mean = 0.0, m2 = 0.0;
         for (uint32_t s = 0; s < J; ++s) {
-            const double ns = static_cast<double>(m.n_traj / J + ((m.n_traj % J) > s ? 1 : 0));
+            // runs of subset s: ids t = s mod J in [t_first, t_first + n_traj), as the number below
+            // the end minus the number below the start (ids below x in subset s: x/J + (x mod J > s))
+            const uint64_t x1 = m.t_first + m.n_traj, x0 = m.t_first;
+            const double ns = static_cast<double>((x1 / J + ((x1 % J) > s ? 1 : 0)) - (x0 / J + ((x0 % J) > s ? 1 : 0)));
             const double rel = exp(V[RL.jk_lse_w + static_cast<uint64_t>(s) * m.n_rows + lr] - l) * (nt / ns);
             const double dlt = rel - mean;
             mean += dlt / static_cast<double>(s + 1);

@@ -141,6 +141,8 @@ int validate(const pyfpt_instance &I, int i) {
     if (std::isnan(I.phi_esc) || I.phi_esc < 0) return fail(PYFPT_EINVAL, "instance %d: bad phi_esc", i);
     if (I.phi_esc != 0 && !(I.phi_esc > I.phi_in)) return fail(PYFPT_EINVAL, "instance %d: need phi_esc > phi_in", i);
     if (I.k_max >= (1ull << 32)) return fail(PYFPT_EINVAL, "instance %d: k_max must be < 2^32", i);
+    if (I.n_traj > UINT64_MAX - I.t_first)
+        return fail(PYFPT_EINVAL, "instance %d: t_first + n_traj exceeds 2^64 - 1", i);
     switch (P.kind) {
     case PYFPT_POT_QUADRATIC:
     case PYFPT_POT_QUADRATIC_BUMP:
@@ -296,6 +298,7 @@ int prepare(const pyfpt_instance *ins, int n_inst, Prepared &P) {
         D.dump_slot = static_cast<uint32_t>(i);
         D.k_center = static_cast<uint32_t>(std::min(expected_steps(I, k_max), 4294967295.0));
         D.n_traj = I.n_traj;
+        D.t_first = I.t_first;
         for (int j = 0; j <= I.bins.n_bins; ++j) {
             P.thr.push_back(threshold(I.bins.edges[j], I.dN));
             P.edges.push_back(I.bins.edges[j]);
@@ -306,6 +309,7 @@ int prepare(const pyfpt_instance *ins, int n_inst, Prepared &P) {
         M.n_bins = D.n_bins;
         M.edge_base = thr_base;
         M.n_traj = I.n_traj;
+        M.t_first = I.t_first;
         P.rl[i] = result_layout(D.n_bins, P.n_sub);
         M.counts_off = P.counts_total;
         M.values_off = P.values_total;
@@ -808,6 +812,7 @@ int pyfpt_run(const pyfpt_potential *pot, double phi_in, double phi_end, double 
         I.k_max = opt->k_max;
         I.phi_esc = opt->phi_esc;
         I.stream = opt->stream_id;
+        I.t_first = opt->t_first;
     }
     return pyfpt_run_batch(&I, 1, seed, out, opt);
 }
@@ -1045,6 +1050,7 @@ int pyfpt_train_proposal(const pyfpt_instance *inst, uint64_t seed, const pyfpt_
     pyfpt_instance I = *inst;
     I.bias.mlp.params = bf.p;
     I.n_traj = cfg->n_sample;
+    I.t_first = 0;                 // each round draws runs 0 .. n_sample - 1 (the dump index is the id)
     const uint64_t ns = cfg->n_sample;
     DevBuf dk, dlw, dphi, dst;
     if ((rc = dk.alloc(4 * ns)) || (rc = dlw.alloc(8 * ns)) || (rc = dphi.alloc(4 * ns)) || (rc = dst.alloc(4 * ns)))

@@ -67,6 +67,7 @@ def _instance(lib, keep, **kw):
     ("edges", np.array([0.0, 1.0, 1.0])),
     ("edges", np.array([0.0, math.inf])),
     ("A", math.inf),
+    ("t_first", (1 << 64) - 100),   # t_first + n_traj past 2^64 - 1
 ])
 def test_invalid_inputs_rejected_without_device(lib, field, value):
     keep = []

@@ -6,6 +6,7 @@ counts per row and per jackknife subset; binary64 log-sums within 1e-12
 relative (only the summation order differs); log-weights within the
 1e-5 relative tolerance a fortiori.
 """
+import dataclasses
 import math
 import os
 import sys
@@ -34,7 +35,7 @@ def fpt():
 
 def _oracle(inst, n=None, stride=1):
     n = inst.n_traj if n is None else n
-    tr = O.simulate(to_model(inst), SEED, n, t0=0, stride=stride)
+    tr = O.simulate(to_model(inst), SEED, n, t0=inst.t_first, stride=stride)
     return tr
 
 
@@ -102,6 +103,9 @@ def test_edge_cases(fpt):
         "bump": W.with_runs(W.c5(), 64),
         "power": W.Instance("pow", m=0.01, phi_in=5.0, bias=W.BIAS_POWER, A=2e-5, p=3, dN=1e-3, n_traj=400,
                             edges=np.linspace(5.6, 6.0, 41)),
+        # run ids across 2^32 (the counter's high word) and up to the last id 2^64 - 1
+        "ids_across_2^32": dataclasses.replace(W.with_runs(W.c1(), 300), t_first=(1 << 32) - 150),
+        "ids_at_the_top": dataclasses.replace(W.with_runs(W.c1(), 300), t_first=(1 << 64) - 1 - 300),
     }
     for name, inst in cases.items():
         _print_case("edge", name=name, n=inst.n_traj)
@@ -114,6 +118,25 @@ def test_edge_cases(fpt):
             assert res.count[-2] == inst.n_traj and res.total_steps == 7 * inst.n_traj
         if name == "escape":
             assert res.count[-1] > 0
+
+
+def test_id_range_shards_add_up(fpt):
+    """One instance run as two id-range shards (as two launches, or two devices, would run it):
+    counts and jackknife counts add exactly, the log-sum-exp sums combine, and each shard is
+    the oracle's runs of its ids."""
+    full = W.with_runs(W.c2()[0], 3000)
+    a = dataclasses.replace(full, n_traj=1234)
+    b = dataclasses.replace(full, n_traj=3000 - 1234, t_first=1234)
+    rf, _, _ = fpt.run(full, SEED, **CFG)
+    ra, da, _ = fpt.run(a, SEED, dump_n=a.n_traj, **CFG)
+    rb, db, _ = fpt.run(b, SEED, dump_n=b.n_traj, **CFG)
+    assert_dump_matches(db, _oracle(b))
+    assert np.array_equal(ra.count + rb.count, rf.count)
+    assert np.array_equal(ra.jk_count + rb.jk_count, rf.jk_count)
+    assert ra.total_steps + rb.total_steps == rf.total_steps
+    both = np.isfinite(ra.lse_w) & np.isfinite(rb.lse_w)
+    assert both.any()
+    assert np.allclose(np.logaddexp(ra.lse_w, rb.lse_w)[both], rf.lse_w[both], rtol=1e-12, atol=1e-12)
 
 
 def test_single_entry_point_matches_batch(fpt):
