@@ -82,6 +82,16 @@ def test_invalid_inputs_rejected_without_device(lib, field, value):
     assert len(lib.load().pyfpt_last_error()) > 0
 
 
+def test_batch_size_limits(lib):
+    """A batch holds 1 .. 1024 instances; 0 and 1025 are rejected before any device work."""
+    keep = []
+    one = _instance(lib, keep)
+    for n in (0, 1025):
+        arr = (lib.pyfpt_instance * max(n, 1))(*([one] * max(n, 1)))
+        res = (lib.pyfpt_result * max(n, 1))()
+        assert lib.load().pyfpt_run_batch(arr, n, 0, res, None) == lib.PYFPT_EINVAL, n
+
+
 def test_mixed_kinds_unsupported(lib):
     keep = []
     a = _instance(lib, keep)

@@ -139,6 +139,19 @@ def test_id_range_shards_add_up(fpt):
     assert np.allclose(np.logaddexp(ra.lse_w, rb.lse_w)[both], rf.lse_w[both], rtol=1e-12, atol=1e-12)
 
 
+def test_largest_batch(fpt):
+    """1024 instances (the batch limit) of 24 runs each, different streams and starting points,
+    in one launch: every run accounted for, and sampled instances' runs match the oracle bit for
+    bit."""
+    insts = [dataclasses.replace(W.with_runs(W.c1(), 24), stream=i, phi_in=5.0 + 0.0005 * (i % 97),
+                                 edges=np.linspace(5.6, 6.0, 11)) for i in range(1024)]
+    _print_case("largest batch", n_inst=len(insts))
+    results, dumps, _ = fpt.run_batch(insts, SEED, dump_n=24, block=256, wg_per_cu=2, chunk=1)
+    assert all(int(r.count.sum()) == 24 for r in results)
+    for i in (0, 1, 511, 1023):
+        assert_dump_matches(dumps[i], _oracle(insts[i]))
+
+
 def test_single_entry_point_matches_batch(fpt):
     inst = W.with_runs(W.c2()[0], 2000)
     a = fpt.run_single_abi(inst, SEED)
