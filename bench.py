@@ -77,6 +77,11 @@ def parse():
     p.add_argument("--c5-total", type=int, default=1_000_000_000)
     p.add_argument("--c5-launches", type=int, default=7, help="launches the amplitudes are split over")
     p.add_argument("--c5-save", type=str, default="", help="write the per-amplitude result tables to this .npz")
+    p.add_argument("--c5-learned", type=int, default=100_000_000,
+                   help="runs of a learned proposal added to the combination (0: fixed amplitudes only)")
+    p.add_argument("--c5-target", type=float, default=24.5, help="window centre N* of the learned proposal")
+    p.add_argument("--c5-curriculum", type=str, default="17,18,19,20,21,22,23,24",
+                   help="window centres the learned proposal is trained through before N*")
     p.add_argument("--mlp-sampler", action="store_true",
                    help="time the learned-bias sampler alone (untrained network, r ~ 1) on the diffusion case")
     p.add_argument("--c3", action="store_true",
@@ -143,8 +148,10 @@ def window_stats(res, lo, hi):
 def c5_run(args):
     """Bump potential V = m^2 phi^2/2 [1 + a exp(-(phi - phi0)^2/(2 w^2))], m = 0.05, a = 0.02,
     phi0 = 4, w = 0.1, phi_in = 8, wall at 12, dN = 1e-4, 500 bins: the runs split over noise-scaled
-    amplitudes A = 0..6 (one noise stream each), run in persistent launches, then combined bin by
-    bin (pyfpt_combine)."""
+    amplitudes A = 0..6 (one noise stream each), run in persistent launches, plus a learned proposal
+    aimed beyond their reach (args.c5_learned runs), all combined bin by bin (pyfpt_combine), the
+    fixed amplitudes serving as the fallback wherever the learned proposal has no trusted
+    estimate."""
     import numpy as np
     import torch
     import paper_2206_11234_amd as F
@@ -166,6 +173,10 @@ def c5_run(args):
         print(f"[c5] amplitudes {[insts[i].A for i in g]}: {tm[0] / 1e3:.1f} s", file=sys.stderr, flush=True)
     wall = time.perf_counter() - t0
     steps = sum(r.total_steps for r in results)
+    learned = None
+    if args.c5_learned > 0:
+        learned = c5_learned_run(args, insts[0], results)
+        results.append(learned.pop("result"))
     # lognormal estimates gated bin by bin (the drift-dominated regime of Sec. 2.4), the naive
     # estimate where a bin fails its gate; with 500 bins and 1e8 runs per amplitude a whole-result
     # gate fails by chance
@@ -178,7 +189,8 @@ def c5_run(args):
     e = results[0].edges
     good = ok & (el < 0.5 * math.log(10.0))          # bins known to better than half a decade
     deepest = int(np.nonzero(good)[0].max()) if good.any() else -1
-    out = {"workload": "C5 bump potential, multi-bias A = 0..6, dN = 1e-4, 500 bins",
+    out = {"workload": "C5 bump potential, multi-bias A = 0..6" + (" + learned proposal" if learned else "") +
+                       ", dN = 1e-4, 500 bins",
            "runs": sum(r.n_traj for r in results), "steps": steps, "wall_s": wall, "kernel_ms": kern_ms, "launches": len(groups),
            "traj_steps_per_s": steps / wall,
            "gate_passed": [bool(r.lognormal_accepted()) for r in results],
@@ -186,7 +198,60 @@ def c5_run(args):
            "reach_log10_p": float(lp[deepest] / math.log(10)) if deepest >= 0 else None,
            "reach_err_log10": float(el[deepest] / math.log(10)) if deepest >= 0 else None,
            "reach_N": float(0.5 * (e[deepest] + e[deepest + 1])) if deepest >= 0 else None}
+    if learned is not None:
+        out["learned"] = learned
     print(json.dumps(out), flush=True)
+
+
+def c5_learned_run(args, base, fixed_results):
+    """The learned proposal on the bump potential: a network started at r = 2 is trained through
+    windows of half-width 0.3 in N centred at the curriculum points and then N* (cross entropy,
+    tempered path weights), then run with args.c5_learned runs on its own noise stream.  Returns
+    its result and, over the window bins around N*, its Kish ESS per 1e6 runs beside each fixed
+    amplitude's."""
+    import dataclasses
+    import numpy as np
+    import torch
+    import paper_2206_11234_amd as F
+    import workloads as W
+
+    target = args.c5_target
+    v = np.zeros(W.MlpParams.N_PARAMS, np.float32)
+    v[:4480] = np.random.default_rng(0).normal(0.0, 1e-2, 4480)
+    v[4480] = 2.0
+    p0 = W.MlpParams(W.bf16_round(v), in_mean=(8.0, target, target), in_inv_scale=(0.25, 0.1, 0.1),
+                     out_scale=1.0, eval_every=args.eval_every)
+    inst0 = dataclasses.replace(base, name="C5_learned", bias=W.BIAS_MLP, A=0.0, mlp=p0, target_N=target,
+                                stream=len(fixed_results), n_traj=args.c5_learned)
+    theta = p0.values_f32()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rounds = []
+    stages = [float(c) for c in args.c5_curriculum.split(",") if c] + [target]
+    for si, centre in enumerate(stages):
+        theta, _, rep = F.train_proposal(dataclasses.replace(inst0, target_N=centre), args.train_seed + 100 * si, theta,
+                                         window=(centre - 0.3, centre + 0.3), n_sample=args.n_sample,
+                                         rounds=args.rounds, steps=args.train_steps, max_paths=args.max_paths,
+                                         lr=args.lr, objective=1, temper=args.temper)
+        for r in rep:
+            r["centre"] = centre
+            print(f"[c5] train round: {json.dumps(r)}", file=sys.stderr, flush=True)
+        rounds += rep
+    train_s = time.perf_counter() - t0
+    inst = dataclasses.replace(inst0, mlp=dataclasses.replace(p0, values=theta))
+    res, _, tm = F.run(inst, 0, block=256, wg_per_cu=2, chunk=1, timing=True)
+    print(f"[c5] learned: {tm[0] / 1e3:.1f} s", file=sys.stderr, flush=True)
+    e = res.edges
+    j = [i for i in range(len(e) - 1) if e[i] >= target - 0.3 and e[i + 1] <= target + 0.3]
+
+    def ess_per_1e6(r):
+        return float(np.nansum(np.exp(2 * r.lse_w[j] - r.lse_w2[j]))) / r.n_traj * 1e6
+
+    return {"result": res, "runs": res.n_traj, "steps": res.total_steps, "kernel_ms": tm[0], "train_s": train_s,
+            "window": [target - 0.3, target + 0.3], "window_bins": len(j),
+            "window_runs": int(res.count[j].sum()), "ess_per_1e6_runs": ess_per_1e6(res),
+            "fixed_ess_per_1e6_runs": {f"A{a.A:g}": ess_per_1e6(r) for a, r in zip(W.c5_multi(), fixed_results)},
+            "train_rounds": rounds}
 
 
 def learned_gain(args):
