@@ -233,7 +233,14 @@ constexpr int TS = 65;  // padded row stride of the [sample][unit] LDS tiles
 
 typedef float f32x16v __attribute__((ext_vector_type(16)));
 
-__global__ __launch_bounds__(64) void fpt_train_bwd_kernel(TrainArgs a, const float *__restrict__ th0) {
+// The three 64x64x64 contractions of a tile run on v_mfma_f32_32x32x2f32 (binary32 products and
+// sums, like the rest of the training network).  Operand layout of that instruction, per lane l
+// and k-step: A[m = l & 31][k = l >> 5], B[k = l >> 5][n = l & 31]; accumulator element q of lane l
+// is D[m = (q & 3) + 8 (q >> 2) + 4 (l >> 5)][n = l & 31] of its 32x32 block.
+__device__ __forceinline__ int acc_row(int q, int lane) { return (q & 3) + 8 * (q >> 2) + 4 * (lane >> 5); }
+
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(1, 1))) void fpt_train_bwd_kernel(TrainArgs a,
+                                                                                          const float *__restrict__ th0) {
     // two [sample][unit] tiles: HA holds h1, then delta1; HB holds h2, then delta2 (34 KB with the
     // inputs and coefficients, so four single-wave workgroups share a CU, one per SIMD)
     __shared__ float HA[64 * TS];
@@ -241,7 +248,20 @@ __global__ __launch_bounds__(64) void fpt_train_bwd_kernel(TrainArgs a, const fl
     __shared__ float XS[64 * 4];
     __shared__ float GS[64];
     const int lane = threadIdx.x;
+    const int col = lane & 31, kh = lane >> 5;
     const double dNd = static_cast<double>(a.dN);
+    // this lane's B fragments of W2 for the whole kernel: WT for h1 W2^T (k = input v, n = unit u),
+    // WN for delta2 W2 (k = unit u, n = input v); and its units' b2
+    float WT[2][32], WN[2][32], b2v[2];
+#pragma unroll
+    for (int nb = 0; nb < 2; ++nb) {
+#pragma unroll
+        for (int ks = 0; ks < 32; ++ks) {
+            WT[nb][ks] = th0[NET_W2 + 64 * (32 * nb + col) + 2 * ks + kh];
+            WN[nb][ks] = th0[NET_W2 + 64 * (2 * ks + kh) + 32 * nb + col];
+        }
+        b2v[nb] = th0[NET_B2 + 32 * nb + col];
+    }
     f32x16v acc[2][2];
 #pragma unroll
     for (int mb = 0; mb < 2; ++mb)
@@ -258,7 +278,8 @@ __global__ __launch_bounds__(64) void fpt_train_bwd_kernel(TrainArgs a, const fl
         TrainRec R{};
         if (valid) R = a.rec[e];
         else R.phi = a.mc.in_mean[0];
-        // forward: h1 into HA, h2 into HB, and r (the same operations as the forward kernel)
+        // forward: h1 into HA (this lane's record), h2 = tanh(W2 h1 + b2) into HB on the matrix
+        // cores (M = record, N = unit, K = input), then r from this lane's row of HB
         float g = 0.0f;
         {
             float x[3], h1[64];
@@ -266,13 +287,36 @@ __global__ __launch_bounds__(64) void fpt_train_bwd_kernel(TrainArgs a, const fl
             net_layer1(th, x, h1);
 #pragma unroll
             for (int u = 0; u < 64; ++u) HA[lane * TS + u] = h1[u];
-            float o = 0.0f;
-#pragma unroll 1
-            for (int u = 0; u < 64; ++u) {
-                const float h2 = net_unit2(th, u, h1);
-                HB[lane * TS + u] = h2;
-                o = __builtin_fmaf(th[NET_W3 + u], h2, o);
+            XS[lane * 4 + 0] = x[0];
+            XS[lane * 4 + 1] = x[1];
+            XS[lane * 4 + 2] = x[2];
+            XS[lane * 4 + 3] = 1.0f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int mb = 0; mb < 2; ++mb) {
+            f32x16v z[2];
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) z[nb][q] = 0.0f;
+#pragma unroll
+            for (int ks = 0; ks < 32; ++ks) {
+                const float av = HA[(32 * mb + col) * TS + 2 * ks + kh];
+                z[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, WT[0][ks], z[0], 0, 0, 0);
+                z[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, WT[1][ks], z[1], 0, 0, 0);
             }
+#pragma unroll
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int q = 0; q < 16; ++q)
+                    HB[(32 * mb + acc_row(q, lane)) * TS + 32 * nb + col] = tanh_hw(z[nb][q] + b2v[nb]);
+        }
+        __syncthreads();
+        {
+            float o = 0.0f;
+#pragma unroll 8
+            for (int u = 0; u < 64; ++u) o = __builtin_fmaf(th[NET_W3 + u], HB[lane * TS + u], o);
             if (valid) {
                 const double r = static_cast<double>(a.mc.out_scale * (o + th[NET_B3]));
                 const uint32_t path = R.pn >> 5;
@@ -280,10 +324,6 @@ __global__ __launch_bounds__(64) void fpt_train_bwd_kernel(TrainArgs a, const fl
                 g = static_cast<float>(a.c[path] * (r * n * dNd - static_cast<double>(R.H)) *
                                        static_cast<double>(a.mc.out_scale) * static_cast<double>(a.rec_weight));
             }
-            XS[lane * 4 + 0] = x[0];
-            XS[lane * 4 + 1] = x[1];
-            XS[lane * 4 + 2] = x[2];
-            XS[lane * 4 + 3] = 1.0f;
             GS[lane] = g;
         }
         __syncthreads();
@@ -329,22 +369,29 @@ __global__ __launch_bounds__(64) void fpt_train_bwd_kernel(TrainArgs a, const fl
             }
         }
         __syncthreads();
-        // delta1 = (W2^T delta2) (1 - h1^2): rows of W2 against this lane's delta2, over its h1
-        {
-            float t1[64];
+        // delta1 = (delta2 W2) (1 - h1^2) on the matrix cores (M = record, N = input, K = unit); each
+        // accumulator element overwrites the h1 it was scaled by (one lane owns each element)
 #pragma unroll
-            for (int v = 0; v < 64; ++v) t1[v] = 0.0f;
-#pragma unroll 1
-            for (int u = 0; u < 64; ++u) {
-                const float d = HB[lane * TS + u];
+        for (int mb = 0; mb < 2; ++mb) {
+            f32x16v z[2];
 #pragma unroll
-                for (int v = 0; v < 64; ++v) t1[v] = __builtin_fmaf(th[NET_W2 + 64 * u + v], d, t1[v]);
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) z[nb][q] = 0.0f;
+#pragma unroll
+            for (int ks = 0; ks < 32; ++ks) {
+                const float av = HB[(32 * mb + col) * TS + 2 * ks + kh];
+                z[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, WN[0][ks], z[0], 0, 0, 0);
+                z[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, WN[1][ks], z[1], 0, 0, 0);
             }
 #pragma unroll
-            for (int v = 0; v < 64; ++v) {
-                const float h = HA[lane * TS + v];
-                HA[lane * TS + v] = t1[v] * __builtin_fmaf(-h, h, 1.0f);
-            }
+            for (int nb = 0; nb < 2; ++nb)
+#pragma unroll
+                for (int q = 0; q < 16; ++q) {
+                    const int idx = (32 * mb + acc_row(q, lane)) * TS + 32 * nb + col;
+                    const float h = HA[idx];
+                    HA[idx] = z[nb][q] * __builtin_fmaf(-h, h, 1.0f);
+                }
         }
         __syncthreads();
         // lane = unit: W1, b1 from delta1
