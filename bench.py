@@ -84,6 +84,8 @@ def parse():
     p.add_argument("--c5-target", type=float, default=24.5, help="window centre N* of the learned proposal")
     p.add_argument("--c5-curriculum", type=str, default="17,18,19,20,21,22,23,24",
                    help="window centres the learned proposal is trained through before N*")
+    p.add_argument("--mlp-wg", type=int, default=2,
+                   help="256-lane workgroups per CU of the learned-bias sampler (waves per SIMD)")
     p.add_argument("--mlp-sampler", action="store_true",
                    help="time the learned-bias sampler alone (untrained network, r ~ 1) on the diffusion case")
     p.add_argument("--c3", action="store_true",
@@ -241,7 +243,7 @@ def c5_learned_run(args, base, fixed_results):
         rounds += rep
     train_s = time.perf_counter() - t0
     inst = dataclasses.replace(inst0, mlp=dataclasses.replace(p0, values=theta))
-    res, _, tm = F.run(inst, 0, block=256, wg_per_cu=2, chunk=1, timing=True)
+    res, _, tm = F.run(inst, 0, block=256, wg_per_cu=args.mlp_wg, chunk=1, timing=True)
     print(f"[c5] learned: {tm[0] / 1e3:.1f} s", file=sys.stderr, flush=True)
     e = res.edges
     j = [i for i in range(len(e) - 1) if e[i] >= target - 0.3 and e[i + 1] <= target + 0.3]
@@ -318,7 +320,7 @@ def learned_gain(args):
     train_s = time.perf_counter() - t0
     p1 = W.MlpParams(theta, in_mean=p0.in_mean, in_inv_scale=p0.in_inv_scale, out_scale=1.0,
                      eval_every=args.eval_every)
-    learned = evaluate(dataclasses.replace(inst0, mlp=p1), "learned", block=256, wg_per_cu=2, chunk=1)
+    learned = evaluate(dataclasses.replace(inst0, mlp=p1), "learned", block=256, wg_per_cu=args.mlp_wg, chunk=1)
     # a fixed bias is a candidate only where its window estimate is trusted by the paper's
     # n_j > 400 criterion (Sec. 2.1); with fewer runs its error estimate is itself unreliable
     cands = [f for f in out["fixed"] if f["gpu_s_to_1pct"] and f["count"] > 400]
@@ -362,10 +364,10 @@ def mlp_sampler_run(args):
                      out_scale=1.0, eval_every=args.eval_every)
     inst = dataclasses.replace(W.c4_instance(p0, n_traj=args.n_eval, target_N=args.target, stream=base.stream),
                                edges=np.linspace(0.0, 400.0, 201))
-    F.run(dataclasses.replace(inst, n_traj=20000), 2, block=256, wg_per_cu=2, chunk=1)   # warm-up
+    F.run(dataclasses.replace(inst, n_traj=20000), 2, block=256, wg_per_cu=args.mlp_wg, chunk=1)   # warm-up
     kms, steps = [], 0
     for s in range(args.steps):
-        res, _, tm = F.run(inst, 2, block=256, wg_per_cu=2, chunk=1, timing=True)
+        res, _, tm = F.run(inst, 2, block=256, wg_per_cu=args.mlp_wg, chunk=1, timing=True)
         kms.append(tm[0])
         steps = res.total_steps
         print(f"[mlp] pass {s}: {tm[0]:.1f} ms", file=sys.stderr, flush=True)
