@@ -222,6 +222,16 @@ typedef struct pyfpt_options {
 int pyfpt_result_layout(int32_t n_bins, int32_t n_sub, pyfpt_layout *out);
 
 /*
+ * The integer step thresholds the kernels bin by (Sec. 2.1: a run that ends after k steps has
+ * N = k dN, and bins are right-closed, N in (e_j, e_{j+1}]): out[j] = max{k >= 0 : fl(k dN) <= e_j}
+ * in binary64, clamped to [0, 2^32 - 1].  A run of k steps falls in bin j exactly when
+ * out[j] < k <= out[j+1], below the range when k <= out[0], above it when k > out[n_edges-1].
+ * edges: n_edges host values; out: n_edges host values.  Host arithmetic; EINVAL for NULL
+ * pointers, n_edges < 1, or dN not finite and > 0.
+ */
+int pyfpt_bin_thresholds(const double *edges, int32_t n_edges, double dN, uint32_t *out);
+
+/*
  * Single instance (the paper's inputs: V via pot, phi_in, phi_end, phi_UV,
  * dN, bias, number of runs; Sec. 2.3 and Sec. 3).
  * EINVAL: NaN/Inf in finite fields; phi_in <= phi_end; phi_uv < phi_in;

@@ -92,7 +92,7 @@ class pyfpt_train_report(ctypes.Structure):
 
 
 # every entry point declared in include/pyfpt.h
-EXPORTS = ("pyfpt_result_layout", "pyfpt_run", "pyfpt_run_batch", "pyfpt_workspace_size",
+EXPORTS = ("pyfpt_result_layout", "pyfpt_bin_thresholds", "pyfpt_run", "pyfpt_run_batch", "pyfpt_workspace_size",
            "pyfpt_mlp_forward", "pyfpt_combine", "pyfpt_proposal_records", "pyfpt_proposal_loss_grad", "pyfpt_train_proposal",
            "pyfpt_device_cus", "pyfpt_last_error")
 
@@ -115,6 +115,7 @@ def load() -> ctypes.CDLL:
     L = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     L.pyfpt_result_layout.argtypes = [ctypes.c_int32, ctypes.c_int32, P(pyfpt_layout)]
+    L.pyfpt_bin_thresholds.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_double, ctypes.c_void_p]
     L.pyfpt_run.argtypes = [P(pyfpt_potential), ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                             P(pyfpt_bias), ctypes.c_uint64, ctypes.c_uint64, P(pyfpt_bins), P(pyfpt_result),
                             P(pyfpt_options)]

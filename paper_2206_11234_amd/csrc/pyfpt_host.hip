@@ -750,6 +750,13 @@ int backward_groups(uint64_t n_rec) {
 
 extern "C" {
 
+int pyfpt_bin_thresholds(const double *edges, int32_t n_edges, double dN, uint32_t *out) {
+    if (!edges || !out || n_edges < 1) return fail(PYFPT_EINVAL, "NULL argument or n_edges < 1");
+    if (!(dN > 0) || !std::isfinite(dN)) return fail(PYFPT_EINVAL, "need finite dN > 0");
+    for (int32_t j = 0; j < n_edges; ++j) out[j] = threshold(edges[j], dN);
+    return PYFPT_OK;
+}
+
 int pyfpt_result_layout(int32_t n_bins, int32_t n_sub, pyfpt_layout *out) {
     if (!out) return fail(PYFPT_EINVAL, "NULL layout");
     if (n_bins < 1) return fail(PYFPT_EINVAL, "n_bins must be >= 1");
