@@ -867,7 +867,7 @@ int pyfpt_mlp_forward(const pyfpt_mlp *mlp, double target_N, const float *phi, c
     return PYFPT_OK;
 }
 
-int pyfpt_combine(const pyfpt_result *res, int32_t n_res, int32_t n_bins, int32_t n_sub, int32_t estimator,
+static int pyfpt_combine_impl(const pyfpt_result *res, int32_t n_res, int32_t n_bins, int32_t n_sub, int32_t estimator,
                   double *log_p, double *err_log, int32_t *n_used) {
     if (!res || !log_p || !err_log || !n_used || n_res < 1) return fail(PYFPT_EINVAL, "NULL argument or n_res < 1");
     if (estimator < 0 || estimator > 3) return fail(PYFPT_EINVAL, "estimator must be 0, 1, 2 or 3");
@@ -926,7 +926,16 @@ int pyfpt_combine(const pyfpt_result *res, int32_t n_res, int32_t n_bins, int32_
     return PYFPT_OK;
 }
 
-int pyfpt_proposal_records(const pyfpt_instance *inst, uint64_t seed, const uint64_t *t_ids, int32_t n_paths,
+int pyfpt_combine(const pyfpt_result *res, int32_t n_res, int32_t n_bins, int32_t n_sub, int32_t estimator,
+                  double *log_p, double *err_log, int32_t *n_used) {
+    try {
+        return pyfpt_combine_impl(res, n_res, n_bins, n_sub, estimator, log_p, err_log, n_used);
+    } catch (...) {
+        return fail(PYFPT_ENOMEM, "host exception (allocation failure)");
+    }
+}
+
+static int pyfpt_proposal_records_impl(const pyfpt_instance *inst, uint64_t seed, const uint64_t *t_ids, int32_t n_paths,
                            int32_t group, int32_t stride, const uint64_t *rec_off, pyfpt_record *rec,
                            uint32_t *k_out, double *lw_out, int32_t *status_out, const pyfpt_options *opt) {
     if (!inst || n_paths < 0 || (n_paths > 0 && (!t_ids || !rec_off || !k_out || !lw_out || !status_out)))
@@ -961,7 +970,17 @@ int pyfpt_proposal_records(const pyfpt_instance *inst, uint64_t seed, const uint
     return PYFPT_OK;
 }
 
-int pyfpt_proposal_loss_grad(const pyfpt_mlp *net, double target_N, double dN, const float *theta,
+int pyfpt_proposal_records(const pyfpt_instance *inst, uint64_t seed, const uint64_t *t_ids, int32_t n_paths,
+                           int32_t group, int32_t stride, const uint64_t *rec_off, pyfpt_record *rec,
+                           uint32_t *k_out, double *lw_out, int32_t *status_out, const pyfpt_options *opt) {
+    try {
+        return pyfpt_proposal_records_impl(inst, seed, t_ids, n_paths, group, stride, rec_off, rec, k_out, lw_out, status_out, opt);
+    } catch (...) {
+        return fail(PYFPT_ENOMEM, "host exception (allocation failure)");
+    }
+}
+
+static int pyfpt_proposal_loss_grad_impl(const pyfpt_mlp *net, double target_N, double dN, const float *theta,
                              const pyfpt_record *rec, uint64_t n_rec, const uint64_t *rec_off, int32_t n_paths,
                              const double *lw0, double n_total, int32_t objective, double temper,
                              double rec_weight, double *loss, double *grad, double *lw_theta,
@@ -1023,7 +1042,20 @@ int pyfpt_proposal_loss_grad(const pyfpt_mlp *net, double target_N, double dN, c
     return PYFPT_OK;
 }
 
-int pyfpt_train_proposal(const pyfpt_instance *inst, uint64_t seed, const pyfpt_train_config *cfg, float *theta,
+int pyfpt_proposal_loss_grad(const pyfpt_mlp *net, double target_N, double dN, const float *theta,
+                             const pyfpt_record *rec, uint64_t n_rec, const uint64_t *rec_off, int32_t n_paths,
+                             const double *lw0, double n_total, int32_t objective, double temper,
+                             double rec_weight, double *loss, double *grad, double *lw_theta,
+                             const pyfpt_options *opt) {
+    try {
+        return pyfpt_proposal_loss_grad_impl(net, target_N, dN, theta, rec, n_rec, rec_off, n_paths, lw0, n_total, objective, temper, rec_weight, loss,
+                                           grad, lw_theta, opt);
+    } catch (...) {
+        return fail(PYFPT_ENOMEM, "host exception (allocation failure)");
+    }
+}
+
+static int pyfpt_train_proposal_impl(const pyfpt_instance *inst, uint64_t seed, const pyfpt_train_config *cfg, float *theta,
                          uint16_t *params_bf16, pyfpt_train_report *report, const pyfpt_options *opt) {
     if (!inst || !cfg || !theta || !params_bf16 || !report) return fail(PYFPT_EINVAL, "NULL argument");
     if (inst->bias.kind != PYFPT_BIAS_MLP) return fail(PYFPT_EINVAL, "the instance's bias must be the learned bias");
@@ -1069,14 +1101,15 @@ int pyfpt_train_proposal(const pyfpt_instance *inst, uint64_t seed, const pyfpt_
     std::vector<uint32_t> hk(ns);
     std::vector<double> hlw(ns);
     std::vector<int32_t> hst(ns);
-    hipEvent_t ev[4];
-    for (auto &e : ev) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
+    hipEvent_t ev[4] = {};
     struct EvFree {
         hipEvent_t *e;
         ~EvFree() {
-            for (int i = 0; i < 4; ++i) (void)hipEventDestroy(e[i]);
+            for (int i = 0; i < 4; ++i)
+                if (e[i]) (void)hipEventDestroy(e[i]);
         }
     } evfree{ev};
+    for (auto &e : ev) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
     int64_t t_adam = 0;
     for (int round = 0; round < cfg->rounds; ++round) {
         pyfpt_train_report &R = report[round];
@@ -1227,6 +1260,15 @@ int pyfpt_train_proposal(const pyfpt_instance *inst, uint64_t seed, const pyfpt_
     HIP_TRY(hipMemcpyAsync(params_bf16, bf.p, 2ull * NET_N_PARAMS, hipMemcpyDeviceToHost, stream), "download params");
     HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
     return PYFPT_OK;
+}
+
+int pyfpt_train_proposal(const pyfpt_instance *inst, uint64_t seed, const pyfpt_train_config *cfg, float *theta,
+                         uint16_t *params_bf16, pyfpt_train_report *report, const pyfpt_options *opt) {
+    try {
+        return pyfpt_train_proposal_impl(inst, seed, cfg, theta, params_bf16, report, opt);
+    } catch (...) {
+        return fail(PYFPT_ENOMEM, "host exception (allocation failure)");
+    }
 }
 
 int pyfpt_device_cus(int32_t *cus) {
