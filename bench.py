@@ -38,7 +38,7 @@ OPS_PER_STEP = 27 + 10 + 1.5 + 32
 # HBM bytes per launch of the step kernel on this workload: rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1
 # (factors read off a plain 1 GiB copy, `--copy-calibration`), summaries under profiles/.
 # Reset to None whenever the step kernel changes until the counters are taken again.
-TRAFFIC = (602499.5 * 1048576 / 524302.4 + 2744400.1 * 1.0) * 1024
+TRAFFIC = (602802.25 * 1.99994 + 2741887.5 * 1.0) * 1024
 
 
 def parse():
