@@ -82,6 +82,33 @@ def test_constant_network_sampler_bit_exact(fpt, every):
     assert_dump_matches(dump, tr)
 
 
+@pytest.mark.parametrize("every", [4, 16])
+def test_bump_potential_constant_network_bit_exact(fpt, every):
+    """The learned bias on the bump potential of the large run (the kernel variant that run
+    uses): a constant network r = 2 reproduces the oracle's noise-scaled bias A = 2 bit for bit,
+    and a random network matches the oracle's network-driven runs as closely as on the quadratic
+    potential."""
+    import dataclasses
+    from helpers import assert_dump_matches
+    base = dataclasses.replace(W.with_runs(W.c5(), 48), bias=W.BIAS_NOISE_SCALED, A=2.0, stream=3)
+    v = np.zeros(W.MlpParams.N_PARAMS, np.float32)
+    v[4480] = 0.5
+    const = dataclasses.replace(base, bias=W.BIAS_MLP, A=0.0, target_N=20.0,
+                                mlp=W.MlpParams(v, out_scale=4.0, eval_every=every))
+    res, dump, _ = fpt.run(const, 0, block=256, wg_per_cu=2, chunk=1, dump_n=const.n_traj)
+    assert_dump_matches(dump, O.simulate(to_model(base), 0, base.n_traj))
+    rnd = dataclasses.replace(const, mlp=W.MlpParams.random(5, 1.0, in_mean=(8.0, 20.0, 20.0),
+                                                            in_inv_scale=(0.25, 0.1, 0.1), out_scale=1.0,
+                                                            eval_every=every))
+    res, dump, _ = fpt.run(rnd, 0, block=256, wg_per_cu=2, chunk=1, dump_n=rnd.n_traj)
+    tr = O.simulate(to_model(rnd), 0, rnd.n_traj)
+    same = dump.k[:rnd.n_traj].astype(np.uint64) == tr.k
+    print(f"bump, random network, every {every}: identical step counts {same.mean():.3f}")
+    assert same.mean() > 0.9
+    lw_rel = np.abs(dump.lw[same] - tr.lw[same]) / np.maximum(1.0, np.abs(tr.lw[same]))
+    assert np.median(lw_rel) < 3e-4
+
+
 def test_learned_bias_batches_match_single_runs(fpt):
     """Two learned-bias instances sharing a network in one batch (the general kernel) give each
     instance's runs exactly as a launch of that instance alone (the single-instance kernel), and
