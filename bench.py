@@ -38,6 +38,10 @@ OPS_PER_STEP = 27 + 10 + 1.5 + 32
 # HBM bytes per launch of the step kernel on this workload: rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1
 # (factors read off a plain 1 GiB copy, `--copy-calibration`), summaries under profiles/.
 # Reset to None whenever the step kernel changes until the counters are taken again.
+# Seed of the learned-vs-fixed evaluation runs: apart from every training seed (train_seed + 100 s
+# + round) and every selection pilot seed (those + 2^30 + c), so the evaluated proposal does not
+# depend on the evaluation's noise.
+EVAL_SEED = 99991
 TRAFFIC = (602802.25 * 1.99994 + 2741887.5 * 1.0) * 1024
 
 
@@ -71,6 +75,9 @@ def parse():
     p.add_argument("--objective", type=int, default=1, help="0: log M2, 1: cross entropy")
     p.add_argument("--temper", type=float, default=0.5, help="w_0^temper in the path weights")
     p.add_argument("--train-seed", type=int, default=1)
+    p.add_argument("--final-rounds", type=int, default=6, help="rounds of the final stage of the far-tail training (the C5 proposal uses --rounds)")
+    p.add_argument("--select-pilot", type=int, default=200_000,
+                   help="pilot runs scoring the final stage's candidate networks (0: keep the last)")
     p.add_argument("--stride", type=int, default=1, help="record stride of the training sums")
     p.add_argument("--curriculum", type=str, default="60,100,140",
                    help="comma-separated window centres trained in turn before the target")
@@ -236,7 +243,8 @@ def c5_learned_run(args, base, fixed_results):
         theta, _, rep = F.train_proposal(dataclasses.replace(inst0, target_N=centre), args.train_seed + 100 * si, theta,
                                          window=(centre - 0.3, centre + 0.3), n_sample=args.n_sample,
                                          rounds=args.rounds, steps=args.train_steps, max_paths=args.max_paths,
-                                         lr=args.lr, objective=1, temper=args.temper)
+                                         lr=args.lr, objective=1, temper=args.temper,
+                                         select=args.select_pilot if si == len(stages) - 1 else 0)
         for r in rep:
             r["centre"] = centre
             print(f"[c5] train round: {json.dumps(r)}", file=sys.stderr, flush=True)
@@ -263,7 +271,9 @@ def learned_gain(args):
     the fixed noise-scaled bias scan, on the diffusion-dominated quadratic case (m = 1,
     phi_in = 6, wall at 8, dN = 1e-3).  The learned network starts at r = 1 (small random
     weights) and is trained with the tempered cross-entropy objective through a curriculum of
-    windows, on runs of its own proposal; both are evaluated on seed 2."""
+    windows, on runs of its own proposal, with args.final_rounds rounds at the target window;
+    that stage's candidate networks are scored on pilots of args.select_pilot runs.  Both
+    proposals are evaluated on EVAL_SEED, which no training round or pilot uses."""
     import dataclasses
     import numpy as np
     import torch
@@ -279,10 +289,10 @@ def learned_gain(args):
            "n_eval": args.n_eval}
 
     def evaluate(inst, label, **kw):
-        F.run(dataclasses.replace(inst, n_traj=min(inst.n_traj, 20000)), 2, **kw)   # warm-up
+        F.run(dataclasses.replace(inst, n_traj=min(inst.n_traj, 20000)), EVAL_SEED, **kw)   # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res, _, tm = F.run(inst, 2, timing=True, **kw)
+        res, _, tm = F.run(inst, EVAL_SEED, timing=True, **kw)
         wall = time.perf_counter() - t0
         st = window_stats(res, lo, hi)
         st.update(label=label, kernel_ms=tm[0], wall_s=wall, steps=res.total_steps,
@@ -310,9 +320,11 @@ def learned_gain(args):
         st_inst = dataclasses.replace(inst0, target_N=centre)
         theta, bf, r_stage = F.train_proposal(st_inst, args.train_seed + 100 * si, theta,
                                               window=(centre - 6.0, centre + 6.0), n_sample=args.n_sample,
-                                              rounds=args.rounds, steps=args.train_steps, max_paths=args.max_paths,
+                                              rounds=(args.final_rounds or args.rounds) if si == len(stages) - 1
+                                              else args.rounds, steps=args.train_steps, max_paths=args.max_paths,
                                               lr=args.lr, objective=args.objective, temper=args.temper,
-                                              stride=args.stride if args.objective == 1 else 1)
+                                              stride=args.stride if args.objective == 1 else 1,
+                                              select=args.select_pilot if si == len(stages) - 1 else 0)
         for r in r_stage:
             r["centre"] = centre
             print(f"[learned] train round: {json.dumps(r)}", file=sys.stderr, flush=True)

@@ -362,7 +362,10 @@ typedef struct pyfpt_train_config {
     int32_t objective;               /* 0: log M2; 1: cross entropy (see pyfpt_proposal_loss_grad) */
     float temper;                    /* beta in (0, 1] of pyfpt_proposal_loss_grad */
     int32_t stride;                  /* record stride (>= 1; > 1 needs objective 1) */
-    int32_t reserved;
+    int32_t select;                  /* 0, or a pilot size: after the rounds, the starting network and
+                                        each round's end network each draw `select` runs (seeds apart
+                                        from the rounds'), and the one whose window runs have the largest
+                                        Kish ESS is returned */
 } pyfpt_train_config;
 
 typedef struct pyfpt_train_report {
@@ -372,6 +375,9 @@ typedef struct pyfpt_train_report {
     double loss_first, loss_last;    /* objective before the round's first and after its last Adam step */
     double kish_window;              /* sum w_0 over the used window runs squared / sum w_0^2 */
     float ms_sample, ms_records, ms_optimise;
+    int32_t selected;                /* 1 for the round whose end network was returned (select mode) */
+    double pilot_ess;                /* select mode: Kish ESS of the window runs of the pilot of the
+                                        network this round ended with; NaN otherwise */
 } pyfpt_train_report;
 
 /*
@@ -379,7 +385,9 @@ typedef struct pyfpt_train_report {
  * out_scale, eval_every and target_N are used, its params are not): each round draws
  * cfg->n_sample runs from the current network (seed + round), keeps the runs that ended in the
  * window, replays them into records and takes cfg->steps Adam steps on the objective.  theta (host,
- * 4481 binary32) is the starting master copy on entry and the trained one on return;
+ * 4481 binary32) is the starting master copy on entry and the trained one on return (in select
+ * mode, the best-scoring of the starting network and the round ends; the pilots use seeds
+ * seed + 2^30 + c, so an evaluation on another seed stays unbiased);
  * params_bf16 (host, 4481) receives the bfloat16 copy for pyfpt_run.  report has cfg->rounds
  * entries.  EINVAL for a bad configuration.  The call synchronises.
  */

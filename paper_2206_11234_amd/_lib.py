@@ -82,13 +82,14 @@ class pyfpt_train_config(ctypes.Structure):
                 ("max_paths", ctypes.c_int32), ("rounds", ctypes.c_int32), ("steps", ctypes.c_int32),
                 ("group", ctypes.c_int32), ("lr", ctypes.c_float), ("beta1", ctypes.c_float),
                 ("beta2", ctypes.c_float), ("eps", ctypes.c_float), ("objective", ctypes.c_int32),
-                ("temper", ctypes.c_float), ("stride", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("temper", ctypes.c_float), ("stride", ctypes.c_int32), ("select", ctypes.c_int32)]
 
 
 class pyfpt_train_report(ctypes.Structure):
     _fields_ = [("n_window", ctypes.c_int32), ("n_used", ctypes.c_int32), ("n_records", ctypes.c_uint64),
                 ("loss_first", ctypes.c_double), ("loss_last", ctypes.c_double), ("kish_window", ctypes.c_double),
-                ("ms_sample", ctypes.c_float), ("ms_records", ctypes.c_float), ("ms_optimise", ctypes.c_float)]
+                ("ms_sample", ctypes.c_float), ("ms_records", ctypes.c_float), ("ms_optimise", ctypes.c_float),
+                ("selected", ctypes.c_int32), ("pilot_ess", ctypes.c_double)]
 
 
 # every entry point declared in include/pyfpt.h

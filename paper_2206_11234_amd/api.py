@@ -417,9 +417,11 @@ def proposal_loss_grad(params, target_N: float, dN: float, theta, recs: Records,
 
 def train_proposal(inst, seed: int, theta, *, window, n_sample: int, rounds: int, steps: int, max_paths: int = 0,
                    lr: float = 1e-3, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8, objective: int = 0,
-                   temper: float = 1.0, stride: int = 1):
+                   temper: float = 1.0, stride: int = 1, select: int = 0):
     """Train the learned proposal of `inst` (pyfpt_train_proposal).  Returns (theta, bf16 bits,
-    list of per-round report dicts)."""
+    list of per-round report dicts).  select > 0: score the starting network and each round's
+    end network on a pilot of that many runs and return the one with the largest window Kish
+    ESS."""
     _torch()
     keep: list = [{}]
     I = make_instance(inst, 16, keep)
@@ -427,7 +429,7 @@ def train_proposal(inst, seed: int, theta, *, window, n_sample: int, rounds: int
     bf = np.zeros(4481, np.uint16)
     cfg = L.pyfpt_train_config(float(window[0]), float(window[1]), int(n_sample), int(max_paths), int(rounds),
                                int(steps), int(inst.mlp.eval_every), float(lr), float(beta1), float(beta2), float(eps),
-                               int(objective), float(temper), int(stride), 0)
+                               int(objective), float(temper), int(stride), int(select))
     rep = (L.pyfpt_train_report * rounds)()
     opt = L.pyfpt_options()
     opt.stream = ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)

@@ -1072,6 +1072,7 @@ static int pyfpt_train_proposal_impl(const pyfpt_instance *inst, uint64_t seed, 
     if (cfg->stride < 1 || (cfg->objective == 0 && cfg->stride != 1))
         return fail(PYFPT_EINVAL, "stride must be >= 1 (and 1 for objective 0)");
     if (cfg->n_sample >= (1ull << 32)) return fail(PYFPT_EINVAL, "n_sample must be < 2^32");
+    if (cfg->select < 0) return fail(PYFPT_EINVAL, "select must be 0 or a pilot size");
     for (int j = 0; j < NET_N_PARAMS; ++j)
         if (!std::isfinite(theta[j])) return fail(PYFPT_EINVAL, "theta[%d] is not finite", j);
     hipStream_t stream = opt ? static_cast<hipStream_t>(opt->stream) : nullptr;
@@ -1091,16 +1092,18 @@ static int pyfpt_train_proposal_impl(const pyfpt_instance *inst, uint64_t seed, 
     I.n_traj = cfg->n_sample;
     I.t_first = 0;                 // each round draws runs 0 .. n_sample - 1 (the dump index is the id)
     const uint64_t ns = cfg->n_sample;
+    const uint64_t n_pilot = cfg->select > 0 ? static_cast<uint64_t>(cfg->select) : 0;
+    const uint64_t nbuf = std::max(ns, n_pilot);
     DevBuf dk, dlw, dphi, dst;
-    if ((rc = dk.alloc(4 * ns)) || (rc = dlw.alloc(8 * ns)) || (rc = dphi.alloc(4 * ns)) || (rc = dst.alloc(4 * ns)))
+    if ((rc = dk.alloc(4 * nbuf)) || (rc = dlw.alloc(8 * nbuf)) || (rc = dphi.alloc(4 * nbuf)) || (rc = dst.alloc(4 * nbuf)))
         return rc;
     pyfpt_layout lay{};
     if ((rc = pyfpt_result_layout(I.bins.n_bins, I.bins.n_sub ? I.bins.n_sub : kDefaultNsub, &lay))) return rc;
     std::vector<uint64_t> counts(lay.n_counts);
     std::vector<double> values(lay.n_values);
-    std::vector<uint32_t> hk(ns);
-    std::vector<double> hlw(ns);
-    std::vector<int32_t> hst(ns);
+    std::vector<uint32_t> hk(nbuf);
+    std::vector<double> hlw(nbuf);
+    std::vector<int32_t> hst(nbuf);
     hipEvent_t ev[4] = {};
     struct EvFree {
         hipEvent_t *e;
@@ -1111,17 +1114,15 @@ static int pyfpt_train_proposal_impl(const pyfpt_instance *inst, uint64_t seed, 
     } evfree{ev};
     for (auto &e : ev) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
     int64_t t_adam = 0;
-    for (int round = 0; round < cfg->rounds; ++round) {
-        pyfpt_train_report &R = report[round];
-        std::memset(&R, 0, sizeof R);
-        const uint64_t seed_r = seed + static_cast<uint64_t>(round);
-        // 1. sample from the current proposal, every run dumped
+    // one sampling pass of the current network, every run dumped and downloaded
+    auto sample = [&](uint64_t seed_r, uint64_t n, float *ms) -> int {
+        I.n_traj = n;
         pyfpt_options so{};
         so.stream = stream;
         so.block = opt && opt->block ? opt->block : 256;
         so.wg_per_cu = opt && opt->wg_per_cu ? opt->wg_per_cu : 2;
         so.chunk = opt && opt->chunk ? opt->chunk : 1;
-        so.dump.n = ns;
+        so.dump.n = n;
         so.dump.stride = 1;
         so.dump.k = dk.as<uint32_t>();
         so.dump.lw = dlw.as<double>();
@@ -1129,21 +1130,52 @@ static int pyfpt_train_proposal_impl(const pyfpt_instance *inst, uint64_t seed, 
         so.dump.status = dst.as<int32_t>();
         pyfpt_result res{counts.data(), values.data(), 0};
         HIP_TRY(hipEventRecord(ev[0], stream), "event");
-        if ((rc = run_batch_impl(&I, 1, seed_r, &res, &so))) return rc;
+        const int r = run_batch_impl(&I, 1, seed_r, &res, &so);
+        if (r) return r;
         HIP_TRY(hipEventRecord(ev[1], stream), "event");
-        HIP_TRY(hipMemcpyAsync(hk.data(), dk.p, 4 * ns, hipMemcpyDeviceToHost, stream), "download k");
-        HIP_TRY(hipMemcpyAsync(hlw.data(), dlw.p, 8 * ns, hipMemcpyDeviceToHost, stream), "download lw");
-        HIP_TRY(hipMemcpyAsync(hst.data(), dst.p, 4 * ns, hipMemcpyDeviceToHost, stream), "download status");
+        HIP_TRY(hipMemcpyAsync(hk.data(), dk.p, 4 * n, hipMemcpyDeviceToHost, stream), "download k");
+        HIP_TRY(hipMemcpyAsync(hlw.data(), dlw.p, 8 * n, hipMemcpyDeviceToHost, stream), "download lw");
+        HIP_TRY(hipMemcpyAsync(hst.data(), dst.p, 4 * n, hipMemcpyDeviceToHost, stream), "download status");
         HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
-        HIP_TRY(hipEventElapsedTime(&R.ms_sample, ev[0], ev[1]), "hipEventElapsedTime");
+        HIP_TRY(hipEventElapsedTime(ms, ev[0], ev[1]), "hipEventElapsedTime");
+        I.n_traj = ns;
+        return PYFPT_OK;
+    };
+    auto in_window = [&](uint64_t t) {
+        const double N = static_cast<double>(hk[t]) * I.dN;
+        return hst[t] == PYFPT_ST_ENDED && N > cfg->window_lo && N <= cfg->window_hi;
+    };
+    // Kish ESS (sum w)^2 / sum w^2 over the window runs of the first n dumped runs
+    auto window_kish = [&](uint64_t n) -> double {
+        double mx = -INFINITY;
+        for (uint64_t t = 0; t < n; ++t)
+            if (in_window(t)) mx = std::max(mx, hlw[t]);
+        if (!(mx > -INFINITY)) return 0.0;
+        double s1 = 0.0, s2 = 0.0;
+        for (uint64_t t = 0; t < n; ++t)
+            if (in_window(t)) {
+                const double e = std::exp(hlw[t] - mx);
+                s1 += e;
+                s2 += e * e;
+            }
+        return s1 * s1 / s2;
+    };
+    // select mode: host copies of the starting network and of each round's end network
+    std::vector<std::vector<float>> cand;
+    if (n_pilot) cand.push_back(std::vector<float>(theta, theta + NET_N_PARAMS));
+    for (int round = 0; round < cfg->rounds; ++round) {
+        pyfpt_train_report &R = report[round];
+        std::memset(&R, 0, sizeof R);
+        R.pilot_ess = NAN;
+        const uint64_t seed_r = seed + static_cast<uint64_t>(round);
+        // 1. sample from the current proposal, every run dumped
+        if ((rc = sample(seed_r, ns, &R.ms_sample))) return rc;
         // 2. the runs that ended in the window (right-closed, as the bins)
         std::vector<uint64_t> ids;
         std::vector<double> lw0;
         double mx = -INFINITY;
         for (uint64_t t = 0; t < ns; ++t) {
-            if (hst[t] != PYFPT_ST_ENDED) continue;
-            const double N = static_cast<double>(hk[t]) * I.dN;
-            if (N > cfg->window_lo && N <= cfg->window_hi) {
+            if (in_window(t)) {
                 R.n_window += 1;
                 // records carry the path index in 27 bits
                 const bool room = cfg->max_paths == 0 ? ids.size() < (1u << 27) - 1u
@@ -1158,6 +1190,7 @@ static int pyfpt_train_proposal_impl(const pyfpt_instance *inst, uint64_t seed, 
         R.n_used = static_cast<int32_t>(ids.size());
         if (ids.empty()) {
             R.loss_first = R.loss_last = -INFINITY;
+            if (n_pilot) cand.push_back(cand.back());
             continue;
         }
         {
@@ -1255,6 +1288,33 @@ static int pyfpt_train_proposal_impl(const pyfpt_instance *inst, uint64_t seed, 
         HIP_TRY(hipMemcpyAsync(&R.loss_last, ls.p, 8, hipMemcpyDeviceToHost, stream), "download loss");
         HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
         HIP_TRY(hipEventElapsedTime(&R.ms_optimise, ev[2], ev[3]), "hipEventElapsedTime");
+        if (n_pilot) {
+            cand.emplace_back(NET_N_PARAMS);
+            HIP_TRY(hipMemcpyAsync(cand.back().data(), th.p, 4ull * NET_N_PARAMS, hipMemcpyDeviceToHost, stream),
+                    "copy theta");
+            HIP_TRY(hipStreamSynchronize(stream), "hipStreamSynchronize");
+        }
+    }
+    if (n_pilot) {
+        // score every candidate on its own pilot of n_pilot runs (seeds apart from the training
+        // rounds') by the Kish ESS of its window runs, and keep the best
+        double best_ess = -1.0;
+        size_t best = 0;
+        for (size_t c = 0; c < cand.size(); ++c) {
+            HIP_TRY(hipMemcpyAsync(th.p, cand[c].data(), 4ull * NET_N_PARAMS, hipMemcpyHostToDevice, stream), "upload theta");
+            HIP_TRY(launch_to_bf16(th.as<float>(), bf.as<uint16_t>(), stream), "launch bf16 copy");
+            float ms = 0.0f;
+            if ((rc = sample(seed + (1ull << 30) + c, n_pilot, &ms))) return rc;
+            const double e = window_kish(n_pilot);
+            if (c > 0) report[c - 1].pilot_ess = e;
+            if (e > best_ess) {
+                best_ess = e;
+                best = c;
+            }
+        }
+        HIP_TRY(hipMemcpyAsync(th.p, cand[best].data(), 4ull * NET_N_PARAMS, hipMemcpyHostToDevice, stream), "upload theta");
+        HIP_TRY(launch_to_bf16(th.as<float>(), bf.as<uint16_t>(), stream), "launch bf16 copy");
+        if (best > 0) report[best - 1].selected = 1;
     }
     HIP_TRY(hipMemcpyAsync(theta, th.p, 4ull * NET_N_PARAMS, hipMemcpyDeviceToHost, stream), "download theta");
     HIP_TRY(hipMemcpyAsync(params_bf16, bf.p, 2ull * NET_N_PARAMS, hipMemcpyDeviceToHost, stream), "download params");

@@ -4,11 +4,12 @@ phi_in = 6, reflecting wall at 8, dN = 1e-3), against the fixed noise-scaled bia
 The window (190, 202] lies near P ~ 1e-30.  With B = A S the weights of the runs that reach
 it spread over many decades (Sec. 3.1 notes this limit of a fixed bias), so a fixed A
 resolves it with a handful of effective samples.  A network trained with the cross-entropy
-objective (window weights w_0^(1/2)) through windows at N = 60, 100, 140 and 196, 8000 window
-runs per round, evaluated once per 16 steps, must (i) estimate P in the window in
+objective (window weights w_0^(1/2)) through windows at N = 60, 100, 140 (3 rounds each) and
+196 (6 rounds), 8000 window runs per round, evaluated once per 16 steps, must (i) estimate P in the window in
 agreement with the pole expansion (Sturm-Liouville solve of the oracle, end moved by
 beta S sqrt(dN) for the discrete monitoring) and (ii) reach a much larger effective sample
-size in the window than the best fixed bias from the same number of runs.
+size in the window than the best fixed bias from the same number of runs (over 100x), and
+(iii) lie much closer to the zero-variance bias of the window than any constant bias does.
 """
 import dataclasses
 import math
@@ -21,6 +22,9 @@ from oracle import refmath as R
 import workloads as W
 
 pytestmark = pytest.mark.gpu
+
+# evaluation runs on a seed no training round (1 + 100 s + round) uses
+EVAL_SEED = 99991
 
 
 @pytest.fixture(scope="module")
@@ -54,16 +58,17 @@ def test_learned_proposal_resolves_the_far_tail(fpt):
     for si, c in enumerate((60.0, 100.0, 140.0, 196.0)):
         print(f"[case] training stage N* = {c}", flush=True)
         theta, _, rep = fpt.train_proposal(dataclasses.replace(inst, target_N=c), 1 + 100 * si, theta,
-                                           window=(c - 6, c + 6), n_sample=200_000, rounds=3, steps=40,
+                                           window=(c - 6, c + 6), n_sample=200_000, rounds=6 if c == target else 3,
+                                           steps=40,
                                            max_paths=8000, lr=3e-3, objective=1, temper=0.5)
         for r in rep:
             print({k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()}, flush=True)
     learned = dataclasses.replace(inst, mlp=dataclasses.replace(p0, values=theta))
-    res_l, _, _ = fpt.run(learned, 2, block=256, wg_per_cu=1, chunk=1)
+    res_l, _, _ = fpt.run(learned, EVAL_SEED, block=256, wg_per_cu=1, chunk=1)
     ess_l, p_l, j = _window(res_l, lo, hi)
     ess_f = []
     for A in (0.8, 1.0):
-        res_f, _, _ = fpt.run(dataclasses.replace(base, A=A), 2, block=512, wg_per_cu=2, chunk=1)
+        res_f, _, _ = fpt.run(dataclasses.replace(base, A=A), EVAL_SEED, block=512, wg_per_cu=2, chunk=1)
         ess_f.append(_window(res_f, lo, hi)[0])
     # pole expansion averaged over the window
     m = O.Model.from_instance(base)
@@ -77,7 +82,7 @@ def test_learned_proposal_resolves_the_far_tail(fpt):
     print(f"learned: window ESS {ess_l:.1f}, log10 P {math.log10(p_l):.3f} (pole expansion {math.log10(p_ref):.3f}, "
           f"Kish rel err {rel:.3f}); fixed A = 0.8, 1.0: ESS {ess_f[0]:.1f}, {ess_f[1]:.1f}")
     assert abs(p_l / p_ref - 1.0) < 4 * rel + 0.05
-    assert ess_l > 10 * max(ess_f)
+    assert ess_l > 100 * max(ess_f)
     # the ceiling: the zero-variance bias for the window (the process conditioned on ending in
     # it, from the pole expansion).  Long before the window it is the quasi-stationary drift;
     # weighted by where the conditioned runs spend that time, the trained network must be closer
@@ -95,4 +100,4 @@ def test_learned_proposal_resolves_the_far_tail(fpt):
         print(f"N = {n:g}: weighted rms |r_net - r*| {math.sqrt(d_l[-1]):.3f}, best constant {math.sqrt(d_c[-1]):.3f}, "
               f"r* at phi = 6, 7, 7.8: {np.round(wb.r(np.array([6.0, 7.0, 7.8]), n), 3)}, "
               f"net {np.round(fpt.mlp_forward(learned.mlp, target, np.array([6, 7, 7.8], np.float32), np.full(3, n, np.float32)), 3)}")
-    assert sum(d_l) < sum(d_c)
+    assert sum(d_l) < 0.3 * sum(d_c)
