@@ -78,7 +78,8 @@ def parse():
     p.add_argument("--final-rounds", type=int, default=6, help="rounds of the final stage of the far-tail training (the C5 proposal uses --rounds)")
     p.add_argument("--select-pilot", type=int, default=200_000,
                    help="pilot runs scoring the final stage's candidate networks (0: keep the last)")
-    p.add_argument("--stride", type=int, default=1, help="record stride of the training sums")
+    p.add_argument("--stride", type=int, default=4,
+                   help="record stride of the far-tail training sums (each kept record counts stride times)")
     p.add_argument("--curriculum", type=str, default="60,100,140",
                    help="comma-separated window centres trained in turn before the target")
     p.add_argument("--c5", action="store_true",
@@ -271,7 +272,8 @@ def learned_gain(args):
     the fixed noise-scaled bias scan, on the diffusion-dominated quadratic case (m = 1,
     phi_in = 6, wall at 8, dN = 1e-3).  The learned network starts at r = 1 (small random
     weights) and is trained with the tempered cross-entropy objective through a curriculum of
-    windows, on runs of its own proposal, with args.final_rounds rounds at the target window;
+    windows, on runs of its own proposal (every args.stride-th record of each run kept, with
+    weight args.stride), with args.final_rounds rounds at the target window;
     that stage's candidate networks are scored on pilots of args.select_pilot runs.  Both
     proposals are evaluated on EVAL_SEED, which no training round or pilot uses."""
     import dataclasses

@@ -5,7 +5,8 @@ The window (190, 202] lies near P ~ 1e-30.  With B = A S the weights of the runs
 it spread over many decades (Sec. 3.1 notes this limit of a fixed bias), so a fixed A
 resolves it with a handful of effective samples.  A network trained with the cross-entropy
 objective (window weights w_0^(1/2)) through windows at N = 60, 100, 140 (3 rounds each) and
-196 (6 rounds), 8000 window runs per round, evaluated once per 16 steps, must (i) estimate P in the window in
+196 (6 rounds), 8000 window runs per round, one record in four kept (each weighted 4),
+evaluated once per 16 steps, must (i) estimate P in the window in
 agreement with the pole expansion (Sturm-Liouville solve of the oracle, end moved by
 beta S sqrt(dN) for the discrete monitoring) and (ii) reach a much larger effective sample
 size in the window than the best fixed bias from the same number of runs (over 100x), and
@@ -59,7 +60,7 @@ def test_learned_proposal_resolves_the_far_tail(fpt):
         print(f"[case] training stage N* = {c}", flush=True)
         theta, _, rep = fpt.train_proposal(dataclasses.replace(inst, target_N=c), 1 + 100 * si, theta,
                                            window=(c - 6, c + 6), n_sample=200_000, rounds=6 if c == target else 3,
-                                           steps=40,
+                                           steps=40, stride=4,
                                            max_paths=8000, lr=3e-3, objective=1, temper=0.5)
         for r in rep:
             print({k: (round(v, 3) if isinstance(v, float) else v) for k, v in r.items()}, flush=True)
