@@ -375,7 +375,8 @@ typedef struct pyfpt_train_report {
     double loss_first, loss_last;    /* objective before the round's first and after its last Adam step */
     double kish_window;              /* sum w_0 over the used window runs squared / sum w_0^2 */
     float ms_sample, ms_records, ms_optimise;
-    int32_t selected;                /* 1 for the round whose end network was returned (select mode) */
+    int32_t selected;                /* 1 for the round whose end network was returned (select mode;
+                                        0 in every round if the starting network was kept) */
     double pilot_ess;                /* select mode: Kish ESS of the window runs of the pilot of the
                                         network this round ended with; NaN otherwise */
 } pyfpt_train_report;
@@ -387,7 +388,8 @@ typedef struct pyfpt_train_report {
  * window, replays them into records and takes cfg->steps Adam steps on the objective.  theta (host,
  * 4481 binary32) is the starting master copy on entry and the trained one on return (in select
  * mode, the best-scoring of the starting network and the round ends; the pilots use seeds
- * seed + 2^30 + c, so an evaluation on another seed stays unbiased);
+ * seed + 2^30 + c, c = 0 for the starting network and r + 1 for round r's, so an evaluation on
+ * another seed stays unbiased);
  * params_bf16 (host, 4481) receives the bfloat16 copy for pyfpt_run.  report has cfg->rounds
  * entries.  EINVAL for a bad configuration.  The call synchronises.
  */

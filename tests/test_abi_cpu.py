@@ -158,7 +158,13 @@ def test_training_and_combine_entry_points_reject_bad_input(lib):
     rep = (lib.pyfpt_train_report * 1)()
     assert L.pyfpt_train_proposal(ctypes.byref(inst), 0, ctypes.byref(cfg), vp(theta), vp(bf),
                                   ctypes.cast(rep, ctypes.c_void_p), ctypes.byref(opt)) == lib.PYFPT_EINVAL
+    cfg = lib.pyfpt_train_config(5.0, 10.0, 100, 0, 1, 1, 4, 1e-3, 0.9, 0.999, 1e-8, 1, 1.0, 1, -1)   # select < 0
+    assert L.pyfpt_train_proposal(ctypes.byref(inst), 0, ctypes.byref(cfg), vp(theta), vp(bf),
+                                  ctypes.cast(rep, ctypes.c_void_p), ctypes.byref(opt)) == lib.PYFPT_EINVAL
+    assert b"select" in L.pyfpt_last_error()
     res = (lib.pyfpt_result * 1)()
     lp = np.zeros(4)
-    assert L.pyfpt_combine(res, 1, 4, 16, 3, vp(lp), vp(lp), vp(lp)) == lib.PYFPT_EINVAL          # estimator 3
+    n_used = np.zeros(4, np.int32)
+    assert L.pyfpt_combine(res, 1, 4, 16, 4, vp(lp), vp(lp), vp(n_used)) == lib.PYFPT_EINVAL      # estimator 4
+    assert b"estimator" in L.pyfpt_last_error()
     assert L.pyfpt_combine(res, 0, 4, 16, 0, vp(lp), vp(lp), vp(lp)) == lib.PYFPT_EINVAL          # no results
