@@ -42,7 +42,7 @@ OPS_PER_STEP = 27 + 10 + 1.5 + 32
 # + round) and every selection pilot seed (those + 2^30 + c), so the evaluated proposal does not
 # depend on the evaluation's noise.
 EVAL_SEED = 99991
-TRAFFIC = (602802.25 * 1.99994 + 2741887.5 * 1.0) * 1024
+TRAFFIC = (602906.0 * 1.99994 + 2742504.75 * 1.0) * 1024
 
 
 def parse():

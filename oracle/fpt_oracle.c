@@ -467,10 +467,11 @@ static int simulate_f32(const oracle_params *P, const consts_f32 *c, uint64_t t,
         }
         float B = r * S;
         float drift = D + B;
-        float det = fmaf(drift, c->dN, phi);
-        float amp = S * c->sq;
-        float nphi = fmaf(amp, xi, det);
-        float inc = fmaf(r, c->hdN, c->sq * xi);
+        /* increment first, then one rounding onto phi */
+        float sxi = c->sq * xi;
+        float dphi = fmaf(S, sxi, drift * c->dN);
+        float nphi = phi + dphi;
+        float inc = fmaf(r, c->hdN, sxi);
         float dlw = -(r * inc);
         lw += (double)dlw;
         if (nphi > c->phi_uv) nphi = c->two_uv - nphi;
@@ -659,10 +660,9 @@ static int64_t records_f32(const oracle_params *P, const consts_f32 *c, uint64_t
         }
         float B = r * S;
         float drift = D + B;
-        float det = fmaf(drift, c->dN, phi);
-        float amp = S * c->sq;
-        float nphi = fmaf(amp, xi, det);
         float sxi = c->sq * xi;
+        float dphi = fmaf(S, sxi, drift * c->dN);
+        float nphi = phi + dphi;
         float inc = fmaf(r, c->hdN, sxi);
         float dlw = -(r * inc);
         lw += (double)dlw;

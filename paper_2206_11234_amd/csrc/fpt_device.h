@@ -282,10 +282,13 @@ __device__ __forceinline__ float em_step(const StepConsts &C, float &phi, uint32
         const float B = r * S;
         drift = D + B;
     }
-    const float det = __builtin_fmaf(drift, C.dN, phi);
-    const float amp = S * C.sq;
-    float nphi = __builtin_fmaf(amp, xi, det);
+    // The whole increment (D + B) dN + S sqrt(dN) xi is formed first and rounded onto phi once.
+    // Adding the deterministic part to phi on its own would round it to phi's grid every step:
+    // at small dN it spans only tens of ulps of phi, and its fraction of an ulp changes so slowly
+    // with phi that the rounding error repeats from step to step instead of averaging out.
     sxi = C.sq * xi;
+    const float inc_phi = __builtin_fmaf(S, sxi, drift * C.dN);
+    float nphi = phi + inc_phi;
     if constexpr (BIAS != BIAS_NONE) {
         const float inc = __builtin_fmaf(r, C.hdN, sxi);
         const float dlw = -(r * inc);

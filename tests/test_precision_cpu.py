@@ -1,0 +1,93 @@
+"""Binary32 step arithmetic against the binary64 reference, workload by workload.
+
+The kernels' step is binary32 with a binary64 weight sum; the paper computes in binary64.  The
+oracle runs the same step in both precisions over the same noise (Philox words, the same
+uniforms, Box-Muller in each precision), and its binary32 mode is the kernels' step bit for bit
+(the GPU parity tests), so comparing the two modes on the same runs states the binary32 error
+of every result:
+
+* paired step counts: the mean of k32 - k64 (a systematic shift of N) and its spread;
+* paired log-weights of the runs that ended in both;
+* the per-bin counts, as a z against the Poisson error of the bin: the runs that a changed step
+  count moves from bin to bin;
+* the per-bin weighted histogram, as a z against the bin's statistical error (Kish), over the
+  bins whose Kish ESS is at least 30: where one or two runs carry a bin's weight its error
+  estimate means little, and a run that moves one step across a bin edge moves the bin by more
+  than that estimate.
+
+Bounds: a mean shift below 1e-3 standard deviations of N (beyond 4 standard errors of the
+paired mean), a spread of k32 - k64 below max(1 step, 2e-3 sd of N), a mean log-weight shift
+below 1e-4 of the spread of ln w, and per-bin z (counts and weighted sums) of rms below 0.5.  A step whose deterministic
+increment is rounded onto phi on its own, at dN = 1e-4, fails the first two on the bump
+potential (a shift of 4e-3 sd and a spread of 5e-3 sd with A = 3).
+"""
+import dataclasses
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import workloads as W
+
+
+def _cases():
+    out = [(W.c1(), 10_000)]
+    for inst in W.c2(1000):
+        if inst.name.startswith("C2_drift") or inst.A == 1.0:
+            out.append((inst, 4000))
+    for inst in W.c3(100)[:8]:
+        out.append((inst, 400))
+    out.append((W.c4_instance(W.c4_params(0, eval_every=16), 100), 1000))
+    c5 = W.c5(100)
+    out.append((c5, 2000))
+    out.append((dataclasses.replace(c5, name="C5_A3", bias=W.BIAS_NOISE_SCALED, A=3.0), 1000))
+    return out
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("inst,n", CASES, ids=[c[0].name for c in CASES])
+def test_binary32_against_binary64(inst, n):
+    m = O.Model.from_instance(inst)
+    a = O.simulate(m, 0, n, mode=O.MODE_F32)
+    b = O.simulate(m, 0, n, mode=O.MODE_F64)
+    ended = (a.status == O.ST_ENDED) & (b.status == O.ST_ENDED)
+    if ended.sum() < 50:
+        # capped or escaping runs: stopped by the same cap in both modes
+        assert np.array_equal(a.status, b.status)
+        print(f"{inst.name}: {ended.sum()} runs ended in both modes (the rest capped); no step statistics")
+        return
+    k32 = a.k[ended].astype(np.int64)
+    k64 = b.k[ended].astype(np.int64)
+    d = k32 - k64
+    sd_k = float(np.std(k64))
+    se = float(np.std(d)) / math.sqrt(d.size)
+    dlw = a.lw[ended] - b.lw[ended]
+    sd_lw = float(np.std(b.lw[ended]))
+    se_lw = float(np.std(dlw)) / math.sqrt(d.size)
+    # per-bin weighted histogram, z against the binary64 bin's Kish relative error
+    ha = O.histogram(a, inst.dN, inst.edges)
+    hb = O.histogram(b, inst.dN, inst.edges)
+    B = len(inst.edges) - 1
+    with np.errstate(invalid="ignore", over="ignore"):
+        ess = np.exp(2 * hb.lse_w[:B] - hb.lse_w2[:B])
+    use = (hb.count[:B] >= 10) & (np.nan_to_num(ess) >= 30)
+    with np.errstate(invalid="ignore", over="ignore"):
+        rel = np.sqrt(np.maximum(np.exp(hb.lse_w2[:B][use] - 2 * hb.lse_w[:B][use]) - 1.0 / n, 0.0))
+    z = (ha.lse_w[:B][use] - hb.lse_w[:B][use]) / np.maximum(rel, 1e-300)
+    z_rms = float(np.sqrt(np.mean(z ** 2))) if z.size else 0.0
+    cb = hb.count[:B].astype(float)
+    cuse = cb >= 10
+    zc = (ha.count[:B][cuse] - cb[cuse]) / np.sqrt(cb[cuse])
+    zc_rms = float(np.sqrt(np.mean(zc ** 2))) if zc.size else 0.0
+    print(f"{inst.name}: {d.size} runs, same k {np.mean(d == 0):.3f}, mean k32-k64 {d.mean():+.3f} +- {se:.3f} steps "
+          f"(sd of k {sd_k:.0f}), sd of k32-k64 {np.std(d):.2f}, mean ln w32 - ln w64 {dlw.mean():+.1e} "
+          f"(sd of ln w {sd_lw:.2f}); counts: {cuse.sum()} bins, z rms {zc_rms:.3f}; "
+          f"weighted: {use.sum()} bins with ESS >= 30, z rms {z_rms:.3f}")
+    assert abs(d.mean()) < 4 * se + 1e-3 * sd_k
+    assert np.std(d) < max(1.0, 2e-3 * sd_k)
+    assert abs(dlw.mean()) < 4 * se_lw + 1e-4 * max(sd_lw, 1.0)
+    assert zc_rms < 0.5
+    assert z_rms < 0.5
