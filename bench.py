@@ -27,14 +27,13 @@ if ROOT not in sys.path:
 # the chip: 32-bit add/mul/logic/move issue at 32 lanes per clock per SIMD, fma, 32x32 integer
 # multiplies, f64 add and conversions at 16 (they occupy two issue slots).
 PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
-# Algorithmic lane operations per trajectory-step of the quadratic, noise-scaled path, counted
-# as the fewest gfx950 VALU instructions the step semantics needs (fma = 1, three-input xor = 1,
-# 32x32->64 multiply = 1):
-#   step 27 (Newton reciprocal 7, drift/noise/bias 6, EM update 3, weight 6, wall 2, k 1, tests 3)
-#   Philox 40/4 (two 32x32->64 multiplies and two three-input xors per round, ten rounds per 4 steps)
-#   radius uniforms 6/4 (shift, or, add), Box-Muller 128/4 (log 25, -2L 1, sqrt 13,
-#   sincos 23 with the quadrant taken from the Philox word, rho*cos/sin 2).
-OPS_PER_STEP = 27 + 10 + 1.5 + 32
+# Algorithmic lane operations per trajectory-step of the quadratic, noise-scaled path: the VALU
+# instructions of the compiled four-step pass of fpt_step_kernel<0,1,false>, loop control and
+# retirement excluded (fma, three-input xor and 32x32->64 multiply one each):
+#   Philox 40/4 (20 v_mad_u64_u32 and 20 v_bitop3_b32: ten rounds per 4 steps)
+#   radius uniforms and the two Box-Muller pairs 119/4 (own log, sqrt and sincos)
+#   the step 114/4 (reciprocal, drift/noise/bias, phi update, weight, wall, k, stopping tests)
+OPS_PER_STEP = (40 + 119 + 114) / 4
 # HBM bytes per launch of the step kernel on this workload: rocprofv3 FETCH_SIZE x 2 + WRITE_SIZE x 1
 # (factors read off a plain 1 GiB copy, `--copy-calibration`), summaries under profiles/.
 # Reset to None whenever the step kernel changes until the counters are taken again.
@@ -42,7 +41,7 @@ OPS_PER_STEP = 27 + 10 + 1.5 + 32
 # + round) and every selection pilot seed (those + 2^30 + c), so the evaluated proposal does not
 # depend on the evaluation's noise.
 EVAL_SEED = 99991
-TRAFFIC = (602906.0 * 1.99994 + 2742504.75 * 1.0) * 1024
+TRAFFIC = (582272.875 * 1.99994 + 2624860.21875 * 1.0) * 1024
 
 
 def parse():

@@ -133,7 +133,12 @@ typedef struct pyfpt_instance {
     uint64_t k_max;                  /* step cap, 1 .. 2^32-1; 0 -> 2^20 */
     uint32_t stream;                 /* noise stream id (Philox counter word 3) */
     uint32_t reserved;
-    double cost_hint;                /* expected steps per run for queue ordering; 0 -> k_max */
+    double cost_hint;                /* expected steps per run, for the queue order (longest
+                                        first) and as the centre of the step-count sums; 0 -> the
+                                        noise-free run length under the applied drift for the
+                                        quadratic potentials with no or noise-scaled bias (k_max
+                                        where that drift does not lead to phi_end), the unbiased
+                                        one for the other biases, k_max for other potentials */
     pyfpt_bins bins;
 } pyfpt_instance;
 

@@ -210,13 +210,26 @@ uint32_t threshold(double e, double dN) {
     return static_cast<uint32_t>(K);
 }
 
+// Expected steps per run: orders the shared work queue (longest first, so that the launch drains
+// on short runs) and centres the step-count sums.  For the quadratic potentials (the bump is a
+// small perturbation of it) this is the noise-free run under the drift actually applied: with the
+// noise-scaled bias B = A S = A c phi, c = m / (2 pi sqrt 6), the path d phi/dN = -2/phi + A c phi
+// takes N = -ln[(2 - A c phi_in^2) / (2 - A c phi_end^2)] / (2 A c) to reach phi_end (the
+// classical (phi_in^2 - phi_end^2)/4 at A = 0).  Where that drift does not point to the end
+// (A c phi_in^2 >= 2), the noise has to carry each run against it, and the run is counted as
+// k_max steps.  Other biases take the unbiased classical value; other potentials k_max.
 double expected_steps(const pyfpt_instance &I, uint64_t k_max) {
-    if (I.cost_hint > 0) return std::min(I.cost_hint, static_cast<double>(k_max));
-    if (I.pot.kind == PYFPT_POT_QUADRATIC || I.pot.kind == PYFPT_POT_QUADRATIC_BUMP) {
-        const double ncl = (I.phi_in * I.phi_in - I.phi_end * I.phi_end) / 4.0;
-        return std::min(ncl / I.dN, static_cast<double>(k_max));
+    const double cap = static_cast<double>(k_max);
+    if (I.cost_hint > 0) return std::min(I.cost_hint, cap);
+    if (I.pot.kind != PYFPT_POT_QUADRATIC && I.pot.kind != PYFPT_POT_QUADRATIC_BUMP) return cap;
+    const double a2 = I.phi_in * I.phi_in, e2 = I.phi_end * I.phi_end;
+    double n = (a2 - e2) / 4.0;
+    if (I.bias.kind == PYFPT_BIAS_NOISE_SCALED && I.bias.A != 0.0) {
+        const double Ac = I.bias.A * I.pot.m / (2.0 * M_PI * std::sqrt(6.0));
+        if (Ac * a2 >= 2.0) return cap;
+        n = -std::log((2.0 - Ac * a2) / (2.0 - Ac * e2)) / (2.0 * Ac);
     }
-    return static_cast<double>(k_max);
+    return std::min(n / I.dN, cap);
 }
 
 int prepare(const pyfpt_instance *ins, int n_inst, Prepared &P) {
