@@ -69,6 +69,22 @@ def test_c2_batch_prefix_bit_exact(fpt):
         assert_histogram_matches(res, h)
 
 
+def test_queue_order_does_not_change_results(fpt):
+    """The shared queue hands out a batch's instances longest expected run first, and a
+    caller's cost_hint overrides the estimate.  The six C2 instances handed out drift first
+    (the reverse of the default, which puts the capped diffusion runs first) give the same
+    runs and histograms as the oracle."""
+    sizes = [1536, 1536, 1536, 700, 300, 300]
+    insts = [dataclasses.replace(W.with_runs(i, n), cost_hint=float(len(sizes) - j))
+             for j, (i, n) in enumerate(zip(W.c2(), sizes))]
+    _print_case("C2 prefix batch, drift instances first", sizes=sizes)
+    results, dumps, _ = fpt.run_batch(insts, SEED, dump_n=max(sizes), dump_stride=1, **CFG)
+    for inst, res, dump in zip(insts, results, dumps):
+        tr = _oracle(inst)
+        assert_dump_matches(dump, tr)
+        assert_histogram_matches(res, O.histogram(tr, inst.dN, inst.edges))
+
+
 @pytest.mark.parametrize("block,wg,chunk", [(64, 8, 1), (256, 4, 4), (1024, 1, 1), (512, 2, 16)])
 def test_launch_shape_does_not_change_results(fpt, block, wg, chunk):
     """Counter-based noise: every run's path depends only on (seed, stream, t), so counts are

@@ -63,6 +63,7 @@ class Instance:
     k_max: int = K_MAX_CAP
     stream: int = 0
     t_first: int = 0          # first run id: runs t_first .. t_first + n_traj - 1
+    cost_hint: float = 0.0    # expected steps per run for the batch queue order (0: the library's estimate)
     edges: np.ndarray = field(default_factory=lambda: np.linspace(0.0, 1.0, 2))
     mlp: object = None        # MlpParams of the learned bias
     target_N: float = 0.0     # N* input of the learned bias
