@@ -435,7 +435,7 @@ def c3_run(args):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
+        print(json.dumps({"error": "the path runs on one GPU: --gpus must be 1 (sharding by run id is described, not launched)"}))
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
