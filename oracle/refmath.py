@@ -589,6 +589,50 @@ def char_poles(model: Model, lam_brackets, dps: int = 50):
     return out
 
 
+def char_function_no_wall(t, model: Model, phi=None, dps: int = 50, alpha=None):
+    """chi(t, phi) of the quadratic model without a wall (eq.
+    eq_appendix_characteristic_function_infinite_UV): only the g solution stays bounded as
+    phi -> infinity, normalised to 1 at phi_end.  On the cut (t = -i y, y > v0/4) pass alpha
+    explicitly to choose the side."""
+    import mpmath as mp
+    mp.mp.dps = dps
+    phi = model.phi_in if phi is None else phi
+    v0, v = _vfun(model, mp)
+    if alpha is None:
+        alpha = mp.sqrt(1 - 4j * mp.mpmathify(t) / v0)
+    a = (-1 + alpha) / 4
+    b = 1 + alpha / 2
+    vp, ve = v(phi), v(model.phi_end)
+    return (vp / ve) ** ((1 - alpha) / 4) * mp.hyp1f1(a, b, -1 / vp) / mp.hyp1f1(a, b, -1 / ve)
+
+
+def pdf_no_wall(N: float, model: Model, phi=None, dps: int = 40) -> float:
+    """P_phi(N) without a wall from the branch cut of chi (eq. eq_appendix_pdf_infinite_UV).
+
+    chi has no poles here; its cut runs along t = -i y for y > v0/4, where alpha^2 = 1 - 4 y/v0
+    is negative.  Inverting with the 1/(2 pi) of eq. eq:PDF:from:chi and wrapping the contour
+    round the cut, across which chi jumps by 2 i Im chi, gives
+        P(N) = -(1/pi) int_{v0/4}^inf Im chi(-i y) e^{-y N} dy,
+    with chi taken on the side where alpha = +i sqrt(4 y/v0 - 1) (the limit from Re t < 0).
+    The paper prints the prefactor as 2; the 1/pi follows from its own inversion formula and is
+    pinned against simulated runs.  Evaluated with mpmath at `dps` digits; the integrand grows
+    with y, so small N (below the bulk of the distribution) is not reachable this way."""
+    import mpmath as mp
+    mp.mp.dps = dps
+    v0, _ = _vfun(model, mp)
+    y0 = v0 / 4
+    N = mp.mpf(N)
+
+    def f(y):
+        kappa = mp.sqrt(4 * y / v0 - 1)
+        return mp.im(char_function_no_wall(None, model, phi, dps, alpha=mp.mpc(0, kappa))) * mp.exp(-y * N)
+
+    # breakpoints: the edge of the cut on the scale 1/N, then decades of y
+    pts = [y0] + [y0 + c / N for c in (1, 10, 100) if c / N < 1] + [mp.mpf(x) for x in (0.05, 0.5, 2, 6) if x > y0]
+    pts = sorted(set(pts)) + [mp.inf]
+    return float(-mp.quad(f, pts) / mp.pi)
+
+
 def char_cumulants(model: Model, h: float = None, dps: int = 60, n_fit: int = 9):
     """The first four cumulants of N as the Taylor coefficients of ln chi(-i s) = ln E[exp(s N)]
     at s = 0, from a polynomial fit through points +-h, +-2h, ... (chi's formula has a removable

@@ -7,6 +7,8 @@
   error in every bin the paper's own criteria trust.
 * Drift-dominated core (m = 0.01, phi_in = 10): the Gaussian of App. B (gamma = kappa = 0) on
   the simulation's lattice, within 4 sigma of the mean.
+* Without a wall (the same potential): the branch-cut integral of App. A's infinite-phi_UV
+  limit, bin by bin, for direct runs and for A = 0.3.
 * The three bias amplitudes of each case estimate the same P(N) where their samples overlap
   (Sec. 3: different A probe different regions of one distribution).
 * Binary32 against binary64: the same runs through the oracle's binary64 mode differ from the
@@ -92,6 +94,40 @@ def test_paper_diffusion_case_matches_pole_expansion(fpt):
         assert np.mean(np.abs(z) < 3) > 0.9, (inst.name, z)
     assert reach[0] > reach[1] > reach[2]
     assert reach[2] < 1e-8
+
+
+def test_no_wall_tail_matches_branch_cut(fpt):
+    """The C2 diffusion potential (m = 1, phi_in = 6) without a wall, where the characteristic
+    function has a branch cut instead of poles (App. A, the infinite-phi_UV limit): trusted bins
+    of width 0.5 from N = 10 out to the reach of 2e6 direct runs and of 1e7 runs with A = 0.3,
+    against the branch-cut integral (end moved by beta S sqrt(dN)) at the bin centre, within 3
+    jackknife errors plus 1 % (the time step and the bin's curvature, both below that here)."""
+    edges = np.arange(6.0, 60.001, 0.5)
+    base = W.Instance("no_wall", m=1.0, phi_in=6.0, dN=1e-3, n_traj=2_000_000, k_max=200_000, edges=edges)
+    insts = [base, W.Instance("no_wall_A0.3", m=1.0, phi_in=6.0, bias=W.BIAS_NOISE_SCALED, A=0.3, dN=1e-3,
+                              n_traj=10_000_000, k_max=200_000, stream=1, edges=edges)]
+    print("[case] no wall, A = 0 and 0.3", flush=True)
+    results, _, _ = fpt.run_batch(insts, 0, block=512, wg_per_cu=2, chunk=1)
+    S_end = base.m * base.phi_end / (2 * math.pi * math.sqrt(6))
+    shifted = O.Model(m=base.m, phi_in=base.phi_in, phi_end=base.phi_end - R.BGK_BETA * S_end * math.sqrt(base.dN))
+    centres = 0.5 * (edges[:-1] + edges[1:])
+    ref = {}
+    reach = []
+    for inst, res in zip(insts, results):
+        use = np.nonzero(_trusted(res) & (edges[:-1] >= 10.0))[0]
+        use = use[::4]                                      # every fourth trusted bin (2 e-folds apart)
+        z = []
+        for j in use:
+            if j not in ref:
+                ref[j] = R.pdf_no_wall(float(centres[j]), shifted)
+            d = math.exp(res.log_p[j]) / ref[j] - 1.0
+            z.append(d / (3.0 * res.rel_err_jk[j] + 0.01))
+            print(f"{inst.name}: N = {centres[j]:.2f}, P {math.exp(res.log_p[j]):.4e} vs {ref[j]:.4e}, "
+                  f"rel err {res.rel_err_jk[j]:.4f}")
+        reach.append(min(ref[j] for j in use))
+        assert len(use) >= 3
+        assert np.all(np.abs(z) < 1.0), (inst.name, z)
+    assert reach[1] < reach[0] / 100
 
 
 def test_c2_diffusion_tail_matches_pole_expansion(c2_results):
