@@ -145,7 +145,8 @@ def cpu_baseline(insts, target_s):
 
 
 def window_stats(res, lo, hi):
-    """Kish ESS and relative errors of the bins inside (lo, hi]."""
+    """Kish ESS and relative errors of the bins inside (lo, hi], with the jackknife relative
+    errors (Sec. 2.1) beside the Kish ones as a cross-check."""
     import numpy as np
     e = res.edges
     j = [i for i in range(len(e) - 1) if e[i] >= lo - 1e-9 and e[i + 1] <= hi + 1e-9]
@@ -153,6 +154,7 @@ def window_stats(res, lo, hi):
     ess = np.exp(2 * lw - lw2)
     rel = np.sqrt(np.maximum(np.exp(lw2 - 2 * lw) - 1.0 / res.n_traj, 0.0))
     return {"bins": len(j), "ess": float(np.nansum(ess)), "median_rel_err": float(np.nanmedian(rel)),
+            "median_rel_err_jk": float(np.nanmedian(res.rel_err_jk[j])),
             "log10_p": float(np.log10(np.nanmean(np.exp(res.log_p[j])))), "count": int(res.count[j].sum())}
 
 
@@ -298,8 +300,9 @@ def learned_gain(args):
         st = window_stats(res, lo, hi)
         st.update(label=label, kernel_ms=tm[0], wall_s=wall, steps=res.total_steps,
                   steps_per_s=res.total_steps / (tm[0] / 1e3))
-        rel = st["median_rel_err"]
-        st["gpu_s_to_1pct"] = (tm[0] / 1e3) * (rel / eps) ** 2 if np.isfinite(rel) and rel > 0 else None
+        for key, rk in (("gpu_s_to_1pct", "median_rel_err"), ("gpu_s_to_1pct_jk", "median_rel_err_jk")):
+            rel = st[rk]
+            st[key] = (tm[0] / 1e3) * (rel / eps) ** 2 if np.isfinite(rel) and rel > 0 else None
         print(f"[learned] {label}: {json.dumps(st)}", file=sys.stderr, flush=True)
         return st
 
@@ -339,9 +342,11 @@ def learned_gain(args):
     cands = [f for f in out["fixed"] if f["gpu_s_to_1pct"] and f["count"] > 400]
     best = min(cands, key=lambda f: f["gpu_s_to_1pct"]) if cands else None
     lg = learned["gpu_s_to_1pct"]
+    lj = learned["gpu_s_to_1pct_jk"]
     out.update(learned=learned, train_s=train_s, train_rounds=rep, best_fixed=best["label"] if best else None,
                gain=(best["gpu_s_to_1pct"] / lg) if (best and lg) else None,
-               gain_with_training=(best["gpu_s_to_1pct"] / (lg + train_s)) if (best and lg) else None)
+               gain_with_training=(best["gpu_s_to_1pct"] / (lg + train_s)) if (best and lg) else None,
+               gain_jk=(best["gpu_s_to_1pct_jk"] / lj) if (best and lj and best["gpu_s_to_1pct_jk"]) else None)
     return out
 
 
@@ -354,7 +359,9 @@ def learned_summary(full):
             "learned_median_rel_err": L["median_rel_err"], "learned_ess": L["ess"],
             "best_fixed": full["best_fixed"], "best_fixed_gpu_s_to_1pct": best["gpu_s_to_1pct"] if best else None,
             "train_s": full["train_s"], "gain": full["gain"], "gain_with_training": full["gain_with_training"],
-            "note": "GPU-s to 1% median relative error over the window = kernel time x (error / 0.01)^2; "
+            "gain_jackknife": full.get("gain_jk"),
+            "note": "GPU-s to 1% median relative error over the window = kernel time x (error / 0.01)^2, "
+                    "errors from the Kish ESS (gain_jackknife: the same with jackknife errors); "
                     "best fixed = lowest among the fixed amplitudes with > 400 window runs"}
 
 
