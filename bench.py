@@ -77,6 +77,9 @@ def parse():
     p.add_argument("--final-rounds", type=int, default=6, help="rounds of the final stage of the far-tail training (the C5 proposal uses --rounds)")
     p.add_argument("--select-pilot", type=int, default=200_000,
                    help="pilot runs scoring the final stage's candidate networks (0: keep the last)")
+    p.add_argument("--eval-dn", type=str, default="",
+                   help="comma-separated further step sizes at which the trained network is evaluated too "
+                        "(the window estimate against the time step; --learned only)")
     p.add_argument("--stride", type=int, default=4,
                    help="record stride of the far-tail training sums (each kept record counts stride times)")
     p.add_argument("--curriculum", type=str, default="60,100,140",
@@ -342,6 +345,14 @@ def learned_gain(args):
     cands = [f for f in out["fixed"] if f["gpu_s_to_1pct"] and f["count"] > 400]
     best = min(cands, key=lambda f: f["gpu_s_to_1pct"]) if cands else None
     lg = learned["gpu_s_to_1pct"]
+    # the same network at smaller time steps: the window estimate's dependence on dN
+    out["learned_dn"] = []
+    for dn in [float(x) for x in args.eval_dn.split(",") if x]:
+        k_max = int(min(1 << 22, 64 * math.ceil(W.MU_SIGMA["C2_diff_T"][0] / dn)))
+        st = evaluate(dataclasses.replace(inst0, mlp=p1, dN=dn, k_max=k_max), f"learned dN={dn:g}",
+                      block=256, wg_per_cu=args.mlp_wg, chunk=1)
+        st["dN"] = dn
+        out["learned_dn"].append(st)
     lj = learned["gpu_s_to_1pct_jk"]
     out.update(learned=learned, train_s=train_s, train_rounds=rep, best_fixed=best["label"] if best else None,
                gain=(best["gpu_s_to_1pct"] / lg) if (best and lg) else None,
