@@ -82,7 +82,7 @@ def test_learned_proposal_resolves_the_far_tail(fpt):
     rel = math.sqrt(max(1.0 / ess_l - 1.0 / res_l.n_traj, 0.0))
     print(f"learned: window ESS {ess_l:.1f}, log10 P {math.log10(p_l):.3f} (pole expansion {math.log10(p_ref):.3f}, "
           f"Kish rel err {rel:.3f}); fixed A = 0.8, 1.0: ESS {ess_f[0]:.1f}, {ess_f[1]:.1f}")
-    assert abs(p_l / p_ref - 1.0) < 4 * rel + 0.05
+    assert abs(p_l / p_ref - 1.0) < 4 * rel + 0.02
     assert ess_l > 100 * max(ess_f)
     # the ceiling: the zero-variance bias for the window (the process conditioned on ending in
     # it, from the pole expansion).  Long before the window it is the quasi-stationary drift;
