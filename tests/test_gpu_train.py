@@ -116,3 +116,30 @@ def test_training_lowers_the_loss(fpt):
     assert rep[0]["loss_last"] < rep[0]["loss_first"]
     assert np.array_equal(bf, (W.bf16_round(theta).view(np.uint32) >> 16).astype(np.uint16))
     assert np.all(np.isfinite(theta))
+
+
+def test_pilot_selection_returns_the_scored_network(fpt):
+    """select > 0 scores the starting network and each round's end network on pilots and returns
+    the best.  Training is deterministic, so the network returned equals the one a run cut at the
+    selected round (without pilots) ends with, bit for bit, and the flags and scores are
+    consistent."""
+    v = np.zeros(W.MlpParams.N_PARAMS, np.float32)
+    v[:4480] = np.random.default_rng(0).normal(0, 1e-2, 4480)
+    v[4480] = 1.0
+    p = W.MlpParams(W.bf16_round(v), in_mean=(5.0, 20.0, 27.5), in_inv_scale=(0.4, 0.05, 0.05), out_scale=1.0,
+                    eval_every=4)
+    inst = W.c4_instance(p, n_traj=1, target_N=27.5)
+    kw = dict(window=(25.0, 30.0), n_sample=20000, steps=20, lr=3e-3, objective=1, temper=0.5)
+    theta, bf, rep = fpt.train_proposal(inst, 11, p.values_f32(), rounds=3, select=20000, **kw)
+    flags = [r["selected"] for r in rep]
+    scores = [r["pilot_ess"] for r in rep]
+    print("selected", flags, "pilot ESS", scores)
+    assert sum(flags) <= 1 and all(np.isfinite(scores))
+    if sum(flags) == 1:
+        s = flags.index(1)
+        assert scores[s] == max(scores)
+        ref, ref_bf, _ = fpt.train_proposal(inst, 11, p.values_f32(), rounds=s + 1, **kw)
+    else:
+        ref, ref_bf = p.values_f32(), (W.bf16_round(p.values_f32()).view(np.uint32) >> 16).astype(np.uint16)
+    assert np.array_equal(theta, ref)
+    assert np.array_equal(bf, ref_bf)
