@@ -223,7 +223,15 @@ typedef struct pyfpt_options {
     float *timing_ms;                /* if not NULL: [0] step kernel, [1] merge kernel (synchronises) */
 } pyfpt_options;
 
-/* Buffer sizes and offsets of one instance's result. */
+/*
+ * Buffer lengths and element offsets of one instance's result for n_bins bins and n_sub
+ * jackknife subsets (0 -> 16): per bin the counts and log-sums of w and w^2 (Sec. 2.1, 2.2), the
+ * jackknife tables, the moments of ln w and the lognormal estimate with its normality p-value
+ * (Sec. 2.4), the estimates log P and their errors; per instance the whole-run sums and
+ * Pearson's r (Sec. 3.4).  The caller allocates counts (u64) and values (f64) of these lengths
+ * and passes them in a pyfpt_result.  Host arithmetic; EINVAL for a NULL out, n_bins < 1, or
+ * n_sub other than 0 or 2 .. 64.
+ */
 int pyfpt_result_layout(int32_t n_bins, int32_t n_sub, pyfpt_layout *out);
 
 /*
@@ -261,8 +269,11 @@ int pyfpt_run(const pyfpt_potential *pot, double phi_in, double phi_end, double 
 int pyfpt_run_batch(const pyfpt_instance *inst, int32_t n_inst, uint64_t seed,
                     pyfpt_result *out, const pyfpt_options *opt);
 
-/* Device workspace needed by pyfpt_run_batch for these instances and options
- * (block/wg_per_cu as resolved; 0 fields take the defaults). */
+/* Device workspace in bytes that pyfpt_run_batch needs for these instances and options
+ * (block/wg_per_cu as resolved; 0 fields take the defaults): the per-workgroup tables, the
+ * queue counter, the instance records and the staging results.  A caller that supplies
+ * opt->workspace must give at least this many bytes (ENOMEM otherwise).  Host arithmetic;
+ * EINVAL as pyfpt_run_batch for invalid instances. */
 int pyfpt_workspace_size(const pyfpt_instance *inst, int32_t n_inst, const pyfpt_options *opt,
                          size_t *bytes);
 
@@ -401,9 +412,12 @@ typedef struct pyfpt_train_report {
 int pyfpt_train_proposal(const pyfpt_instance *inst, uint64_t seed, const pyfpt_train_config *cfg, float *theta,
                          uint16_t *params_bf16, pyfpt_train_report *report, const pyfpt_options *opt);
 
-/* Number of compute units of the current device (0 if none). */
+/* Number of compute units of the current device, which sets the default grid (0 and
+ * EDEVICE if there is none).  EINVAL for a NULL cus. */
 int pyfpt_device_cus(int32_t *cus);
 
+/* Message of the calling thread's last failed call (thread-local; owned by the library, valid
+ * until that thread's next call). */
 const char *pyfpt_last_error(void);
 
 #ifdef __cplusplus
