@@ -73,8 +73,11 @@ def assert_histogram_matches(res, h, rel=1e-12):
     f4 = np.isfinite(lp_ln)
     assert np.array_equal(np.isfinite(res.log_p_ln), f4)
     assert np.all(np.abs(res.log_p_ln[f4] - lp_ln[f4]) <= 1e-8 * np.maximum(1, np.abs(lp_ln[f4])))
-    assert np.all(np.abs(res.rel_err_ln_hi[f4] - hi[f4]) <= 1e-7 * hi[f4] + 1e-12)
-    assert np.all(np.abs(res.rel_err_ln_lo[f4] - lo[f4]) <= 1e-7 * lo[f4] + 1e-12)
+    # the upper error overflows to +inf on both sides when s^2 is large for few runs
+    # (u = sqrt(s^2/n + s^4/(2n - 2)) above ~709); equal values match, infinities included
+    for got, want in ((res.rel_err_ln_hi[f4], hi[f4]), (res.rel_err_ln_lo[f4], lo[f4])):
+        with np.errstate(invalid="ignore"):
+            assert np.all((got == want) | (np.abs(got - want) <= 1e-7 * want + 1e-12))
     pv = h.normal_p[:B]
     f5 = np.isfinite(pv)
     assert np.array_equal(np.isfinite(res.normal_p), f5), (np.nonzero(np.isfinite(res.normal_p) != f5)[0][:5])

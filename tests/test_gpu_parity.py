@@ -214,6 +214,22 @@ def test_full_size_c2_sampled_runs(fpt):
             assert abs(mean_w - 1) < 6 / math.sqrt(ess) + 1e-3, (inst.name, mean_w, ess)
 
 
+def test_c5_top_of_range_bit_exact(fpt):
+    """The bump-potential large run at its full size (1e9 runs over A = 0 .. 6, one instance of
+    1.43e8 runs per amplitude): the last 4096 ids of the A = 0 and A = 6 instances, addressed
+    by run id, in the benchmark's launch shape, every run against the oracle."""
+    n_last = 4096
+    insts = []
+    for inst in (W.c5_multi()[0], W.c5_multi()[6]):
+        insts.append(dataclasses.replace(inst, t_first=inst.n_traj - n_last, n_traj=n_last))
+    _print_case("C5 top of range", t_first=insts[0].t_first, n=n_last)
+    results, dumps, _ = fpt.run_batch(insts, SEED, dump_n=n_last, dump_stride=1, **CFG)
+    for inst, res, dump in zip(insts, results, dumps):
+        tr = _oracle(inst)
+        assert_dump_matches(dump, tr)
+        assert_histogram_matches(res, O.histogram(tr, inst.dN, inst.edges))
+
+
 def test_autotuned_launch_matches(fpt):
     """The autotuner only picks the launch shape: results equal the fixed-shape run."""
     inst = W.with_runs(W.c2()[1], 4000)
