@@ -379,15 +379,16 @@ class Histogram:
         eq_lognormal_bin_pdf_reconstrcuted_weighted_maximum_likelihood), and the relative error
         factors |exp(-+u) - 1|, u = sqrt(s^2/n_j + s^4/(2 n_j - 2)) (eq.
         eq_log_normal_bin_pdf_reconstrcuted_error_maximum_likelihood).  s^2 is the unbiased sample
-        variance.  Returns (log P_hat, rel_lo, rel_hi) per bin, nan where n_j < 2."""
+        variance.  Returns (log P_hat, rel_lo, rel_hi) per bin, nan where n_j < 2; rel_hi is +inf
+        where u exceeds the binary64 range of exp (a wide ln w over few runs)."""
         B = len(self.edges) - 1
         n = self.count[:B].astype(np.float64)
         s2 = self.s2_lnw[:B]
-        with np.errstate(divide="ignore", invalid="ignore"):
+        with np.errstate(divide="ignore", invalid="ignore", over="ignore"):
             lp = np.log(n) + self.mean_lnw[:B] + 0.5 * s2 - np.log(self.widths()) - np.log(self.n_traj)
             u = np.sqrt(s2 / n + s2 * s2 / (2 * n - 2))
-        ok = n >= 2
-        return np.where(ok, lp, np.nan), np.where(ok, -np.expm1(-u), np.nan), np.where(ok, np.expm1(u), np.nan)
+            ok = n >= 2
+            return np.where(ok, lp, np.nan), np.where(ok, -np.expm1(-u), np.nan), np.where(ok, np.expm1(u), np.nan)
 
     def log_p_naive(self):
         """log P_hat_j = log(sum_i w_i / (Delta_j n_total)), n_total = all launched runs."""
