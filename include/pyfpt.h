@@ -269,6 +269,29 @@ int pyfpt_run(const pyfpt_potential *pot, double phi_in, double phi_end, double 
 int pyfpt_run_batch(const pyfpt_instance *inst, int32_t n_inst, uint64_t seed,
                     pyfpt_result *out, const pyfpt_options *opt);
 
+/*
+ * For callers that cannot allocate (code under HIP stream capture, tight serving loops, harnesses
+ * that forbid hipMalloc): pyfpt_run_batch without any allocation.  Same instances, seed, results
+ * and errors as pyfpt_run_batch, with the same kernels; its device scratch (queue counter,
+ * instance records, thresholds, staging results, per-workgroup tables) is a static device array
+ * of PYFPT_NOALLOC_SCRATCH_BYTES that each device the library runs on holds from its first use
+ * until the process ends, and its host bookkeeping comes from a static host arena of 8 MiB.  The
+ * call makes no hipMalloc, hipFree, hipHostMalloc or heap allocation.
+ *   - The caller still owns inst, out (host or device buffers) and the dump arrays.
+ *   - opt->block, opt->chunk and opt->wg_per_cu as given, 0 = the defaults (no autotuning, which
+ *     would allocate); opt->workspace must be NULL and opt->use_graph 0 (EINVAL otherwise).
+ *   - PYFPT_ENOMEM, with the bytes needed, when the batch's tables do not fit the scratch (the
+ *     tables take about n_workgroups x (n_rows x (24 + 12 n_sub) + 128 n_inst) bytes with
+ *     n_rows = sum of (n_bins + 4)); fewer workgroups per CU or fewer bins make them fit.
+ *   - Every call on a device shares that device's scratch and the process's host arena: the call
+ *     holds the library's lock until its work is enqueued, but work enqueued on two streams that
+ *     overlap on one device races on the scratch.  Serialise such calls (one stream, or an event
+ *     between them).  The scratch keeps the last call's contents; the kernels clear what they use.
+ */
+#define PYFPT_NOALLOC_SCRATCH_BYTES (64u << 20)
+int pyfpt_run_batch_noalloc(const pyfpt_instance *inst, int32_t n_inst, uint64_t seed,
+                            pyfpt_result *out, const pyfpt_options *opt);
+
 /* Device workspace in bytes that pyfpt_run_batch needs for these instances and options
  * (block/wg_per_cu as resolved; 0 fields take the defaults): the per-workgroup tables, the
  * queue counter, the instance records and the staging results.  A caller that supplies

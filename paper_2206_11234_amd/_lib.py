@@ -12,6 +12,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpyfpt.so")
 
 PYFPT_OK, PYFPT_EINVAL, PYFPT_ENOMEM, PYFPT_EDEVICE, PYFPT_EUNSUPPORTED = 0, -1, -2, -3, -4
+NOALLOC_SCRATCH_BYTES = 64 << 20   # PYFPT_NOALLOC_SCRATCH_BYTES
 POT_QUADRATIC, POT_QUADRATIC_BUMP, POT_FLAT = 0, 1, 2
 BIAS_NONE, BIAS_NOISE_SCALED, BIAS_POWER, BIAS_MLP = 0, 1, 2, 3
 ST_ENDED, ST_CENSORED, ST_ESCAPED = 1, 2, 3
@@ -93,7 +94,8 @@ class pyfpt_train_report(ctypes.Structure):
 
 
 # every entry point declared in include/pyfpt.h
-EXPORTS = ("pyfpt_result_layout", "pyfpt_bin_thresholds", "pyfpt_run", "pyfpt_run_batch", "pyfpt_workspace_size",
+EXPORTS = ("pyfpt_result_layout", "pyfpt_bin_thresholds", "pyfpt_run", "pyfpt_run_batch", "pyfpt_run_batch_noalloc",
+           "pyfpt_workspace_size",
            "pyfpt_mlp_forward", "pyfpt_combine", "pyfpt_proposal_records", "pyfpt_proposal_loss_grad", "pyfpt_train_proposal",
            "pyfpt_device_cus", "pyfpt_last_error")
 
@@ -122,6 +124,8 @@ def load() -> ctypes.CDLL:
                             P(pyfpt_options)]
     L.pyfpt_run_batch.argtypes = [P(pyfpt_instance), ctypes.c_int32, ctypes.c_uint64, P(pyfpt_result),
                                   P(pyfpt_options)]
+    L.pyfpt_run_batch_noalloc.argtypes = [P(pyfpt_instance), ctypes.c_int32, ctypes.c_uint64, P(pyfpt_result),
+                                          P(pyfpt_options)]
     L.pyfpt_workspace_size.argtypes = [P(pyfpt_instance), ctypes.c_int32, P(pyfpt_options), P(ctypes.c_size_t)]
     L.pyfpt_device_cus.argtypes = [P(ctypes.c_int32)]
     L.pyfpt_mlp_forward.argtypes = [P(pyfpt_mlp), ctypes.c_double, ctypes.c_void_p, ctypes.c_void_p,

@@ -224,8 +224,9 @@ def make_instance(inst, n_sub: int, keep: list) -> L.pyfpt_instance:
 
 def run_batch(instances, seed: int = 0, *, n_sub: int = 16, block: int = 0, chunk: int = 0, wg_per_cu: int = 0,
               use_graph: bool = False, dump_n: int = 0, dump_stride: int = 1, timing: bool = False,
-              torch_workspace: bool = True):
-    """Run a batch of instances in one persistent launch.  Returns (results, dumps, timing_ms)."""
+              torch_workspace: bool = True, noalloc: bool = False):
+    """Run a batch of instances in one persistent launch.  Returns (results, dumps, timing_ms).
+    noalloc: through pyfpt_run_batch_noalloc (static scratch, no autotuning, no workspace)."""
     torch = _torch()
     lib = L.load()
     keep: list = [{}]          # [0]: device copies of networks shared by several instances
@@ -253,7 +254,7 @@ def run_batch(instances, seed: int = 0, *, n_sub: int = 16, block: int = 0, chun
         opt.dump = L.pyfpt_dump(dump_n, dump_stride, dump_t[0].data_ptr(), dump_t[1].data_ptr(),
                                 dump_t[2].data_ptr(), dump_t[3].data_ptr())
     ws_t = None
-    if torch_workspace:
+    if torch_workspace and not noalloc:
         nbytes = ctypes.c_size_t(0)
         L.check(lib.pyfpt_workspace_size(arr, n, ctypes.byref(opt), ctypes.byref(nbytes)))
         ws_t = torch.empty(int(nbytes.value), dtype=torch.uint8, device=dev)
@@ -262,7 +263,8 @@ def run_batch(instances, seed: int = 0, *, n_sub: int = 16, block: int = 0, chun
     tm = (ctypes.c_float * 2)()
     if timing:
         opt.timing_ms = tm
-    L.check(lib.pyfpt_run_batch(arr, n, int(seed), res, ctypes.byref(opt)))
+    entry = lib.pyfpt_run_batch_noalloc if noalloc else lib.pyfpt_run_batch
+    L.check(entry(arr, n, int(seed), res, ctypes.byref(opt)))
     stream.synchronize()
     results = []
     for i, inst in enumerate(instances):

@@ -29,15 +29,15 @@ using namespace fpt;
 
 namespace {
 
-thread_local std::string g_err;
+// Message of the calling thread's last failed call (a fixed buffer: reporting an error never
+// allocates).
+thread_local char g_err[512];
 
 int fail(int code, const char *fmt, ...) {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
     va_end(ap);
-    g_err = buf;
     return code;
 }
 
@@ -70,7 +70,9 @@ struct Device {
     void *pinned = nullptr;
     size_t pinned_bytes = 0;
     hipEvent_t pinned_done = nullptr;
+    hipEvent_t arena_done = nullptr;    // after an upload read from the host arena
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    unsigned char *scratch = nullptr;   // this device's copy of the static scratch array
     // graph cache
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -78,12 +80,15 @@ struct Device {
     std::map<std::string, LaunchCfg> tuned;
 };
 
+constexpr int kMaxDevices = 64;
+
 std::mutex g_mu;
-std::map<int, Device> g_dev;
+Device g_dev[kMaxDevices];
 
 int get_device(Device **out) {
     int id = 0;
     HIP_TRY(hipGetDevice(&id), "hipGetDevice");
+    if (id < 0 || id >= kMaxDevices) return fail(PYFPT_EDEVICE, "device %d beyond the %d devices supported", id, kMaxDevices);
     Device &d = g_dev[id];
     if (d.id < 0) {
         d.id = id;
@@ -94,6 +99,7 @@ int get_device(Device **out) {
         if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, id) != hipSuccess) lds = 65536;
         d.max_lds = static_cast<size_t>(lds);
         HIP_TRY(hipEventCreateWithFlags(&d.pinned_done, hipEventDisableTiming), "hipEventCreate");
+        HIP_TRY(hipEventCreateWithFlags(&d.arena_done, hipEventDisableTiming), "hipEventCreate");
         for (auto &e : d.ev) HIP_TRY(hipEventCreate(&e), "hipEventCreate");
     }
     *out = &d;
@@ -103,16 +109,81 @@ int get_device(Device **out) {
 bool finite(double x) { return std::isfinite(x); }
 
 // ----------------------------------------------------------------------------
+// host arena: while the allocation-free entry point runs (under g_mu, flag set on its thread),
+// the call's bookkeeping (prepared instances, thresholds, queue order, upload image) is carved
+// from this static block instead of the heap; elsewhere the containers use the heap as usual.
+// ----------------------------------------------------------------------------
+constexpr size_t kArenaBytes = 8u << 20;
+alignas(256) unsigned char g_arena[kArenaBytes];
+size_t g_arena_top = 0;
+thread_local bool g_in_arena = false;
+hipEvent_t g_arena_upload = nullptr;    // recorded after the last upload that read the arena
+
+bool in_arena(const void *p) {
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    return c >= g_arena && c < g_arena + kArenaBytes;
+}
+
+void *arena_take(size_t bytes) {
+    const size_t at = align_up(g_arena_top, 64);
+    if (bytes > kArenaBytes - at) return nullptr;
+    g_arena_top = at + bytes;
+    return g_arena + at;
+}
+
+struct ArenaFull {};
+
+template <class T>
+struct ArenaAlloc {
+    using value_type = T;
+    ArenaAlloc() = default;
+    template <class U>
+    ArenaAlloc(const ArenaAlloc<U> &) {}
+    T *allocate(size_t n) {
+        if (g_in_arena) {
+            void *p = n <= kArenaBytes / sizeof(T) ? arena_take(n * sizeof(T)) : nullptr;
+            if (!p) throw ArenaFull{};
+            return static_cast<T *>(p);
+        }
+        return static_cast<T *>(::operator new(n * sizeof(T)));
+    }
+    void deallocate(T *p, size_t) {
+        if (!in_arena(p)) ::operator delete(p);
+    }
+    template <class U>
+    bool operator==(const ArenaAlloc<U> &) const { return true; }
+    template <class U>
+    bool operator!=(const ArenaAlloc<U> &) const { return false; }
+};
+
+template <class T>
+using Vec = std::vector<T, ArenaAlloc<T>>;
+
+// Stable descending order of (key, index) pairs by key, in place (insertion sort: batches hold
+// at most 1024 instances, and it needs no temporary buffer).
+void sort_longest_first(Vec<std::pair<double, int>> &v) {
+    for (size_t i = 1; i < v.size(); ++i) {
+        const std::pair<double, int> x = v[i];
+        size_t j = i;
+        while (j > 0 && v[j - 1].first < x.first) {
+            v[j] = v[j - 1];
+            --j;
+        }
+        v[j] = x;
+    }
+}
+
+// ----------------------------------------------------------------------------
 // validation and preparation
 // ----------------------------------------------------------------------------
 struct Prepared {
-    std::vector<InstDev> inst;
-    std::vector<uint32_t> order;
-    std::vector<uint64_t> vbeg_sorted;
-    std::vector<uint32_t> thr;
-    std::vector<double> edges;
-    std::vector<MergeInst> mi;
-    std::vector<ResultLayout> rl;
+    Vec<InstDev> inst;
+    Vec<uint32_t> order;
+    Vec<uint64_t> vbeg_sorted;
+    Vec<uint32_t> thr;
+    Vec<double> edges;
+    Vec<MergeInst> mi;
+    Vec<ResultLayout> rl;
     TableLayout lay{};
     const uint16_t *mlp_params = nullptr;
     int mlp_every = 1;
@@ -269,7 +340,14 @@ int prepare(const pyfpt_instance *ins, int n_inst, Prepared &P) {
     P.mi.resize(n_inst);
     P.rl.resize(n_inst);
     uint32_t rows = 0, thr_base = 0;
-    std::vector<std::pair<double, int>> cost;
+    size_t n_edges = 0;
+    for (int i = 0; i < n_inst; ++i) n_edges += static_cast<size_t>(ins[i].bins.n_bins) + 1;
+    P.thr.reserve(n_edges);
+    P.edges.reserve(n_edges);
+    P.order.reserve(n_inst);
+    P.vbeg_sorted.reserve(n_inst);
+    Vec<std::pair<double, int>> cost;
+    cost.reserve(n_inst);
     for (int i = 0; i < n_inst; ++i) {
         const pyfpt_instance &I = ins[i];
         const uint64_t k_max = I.k_max ? I.k_max : kDefaultKmax;
@@ -333,7 +411,7 @@ int prepare(const pyfpt_instance *ins, int n_inst, Prepared &P) {
         if (I.n_traj > 0) cost.push_back({expected_steps(I, k_max), i});
     }
     // longest expected runs first (ties: caller order)
-    std::stable_sort(cost.begin(), cost.end(), [](auto &a, auto &b) { return a.first > b.first; });
+    sort_longest_first(cost);
     uint64_t v = 0;
     for (auto &c : cost) {
         P.order.push_back(static_cast<uint32_t>(c.second));
@@ -425,7 +503,8 @@ struct RunCtx {
 };
 
 int run_prepared(Device &d, const Prepared &P, uint64_t seed, const LaunchCfg &cfg_in, const pyfpt_options *opt,
-                 hipStream_t stream, void *ws, size_t ws_bytes, bool use_graph, float *timing) {
+                 hipStream_t stream, void *ws, size_t ws_bytes, bool use_graph, float *timing,
+                 bool noalloc = false) {
     LaunchCfg cfg = cfg_in;
     bool lds = false;
     resolve_cfg(d, P, cfg, lds);
@@ -439,8 +518,14 @@ int run_prepared(Device &d, const Prepared &P, uint64_t seed, const LaunchCfg &c
     if (ws_bytes < m.total) return fail(PYFPT_ENOMEM, "workspace too small: need %zu bytes, have %zu", m.total, ws_bytes);
     unsigned char *W = static_cast<unsigned char *>(ws);
 
-    // upload through the pinned staging buffer
-    if (d.pinned_bytes < m.upload_bytes) {
+    // upload through the pinned staging buffer, or, without allocating, through an image in the
+    // host arena (the caller has waited for the previous arena upload)
+    unsigned char *H = nullptr;
+    if (noalloc) {
+        H = static_cast<unsigned char *>(arena_take(m.upload_bytes));
+        if (!H) return fail(PYFPT_ENOMEM, "upload image of %zu bytes exceeds the host arena (%zu bytes)",
+                            m.upload_bytes, kArenaBytes);
+    } else if (d.pinned_bytes < m.upload_bytes) {
         if (d.pinned) {
             HIP_TRY(hipEventSynchronize(d.pinned_done), "hipEventSynchronize");
             (void)hipHostFree(d.pinned);
@@ -451,7 +536,7 @@ int run_prepared(Device &d, const Prepared &P, uint64_t seed, const LaunchCfg &c
     } else {
         HIP_TRY(hipEventSynchronize(d.pinned_done), "hipEventSynchronize");
     }
-    unsigned char *H = static_cast<unsigned char *>(d.pinned);
+    if (!noalloc) H = static_cast<unsigned char *>(d.pinned);
     std::memset(H, 0, m.upload_bytes);
     std::memcpy(H + (m.inst - m.inst), P.inst.data(), P.inst.size() * sizeof(InstDev));
     std::memcpy(H + (m.order - m.inst), P.order.data(), P.order.size() * 4);
@@ -460,7 +545,12 @@ int run_prepared(Device &d, const Prepared &P, uint64_t seed, const LaunchCfg &c
     std::memcpy(H + (m.edges - m.inst), P.edges.data(), P.edges.size() * 8);
     std::memcpy(H + (m.mi - m.inst), P.mi.data(), P.mi.size() * sizeof(MergeInst));
     HIP_TRY(hipMemcpyAsync(W + m.inst, H, m.upload_bytes, hipMemcpyHostToDevice, stream), "upload");
-    HIP_TRY(hipEventRecord(d.pinned_done, stream), "hipEventRecord");
+    if (noalloc) {
+        HIP_TRY(hipEventRecord(d.arena_done, stream), "hipEventRecord");
+        g_arena_upload = d.arena_done;
+    } else {
+        HIP_TRY(hipEventRecord(d.pinned_done, stream), "hipEventRecord");
+    }
 
     StepArgs sa{};
     sa.inst = reinterpret_cast<const InstDev *>(W + m.inst);
@@ -680,6 +770,78 @@ int run_batch_impl(const pyfpt_instance *ins, int n_inst, uint64_t seed, pyfpt_r
 }
 
 // ----------------------------------------------------------------------------
+// allocation-free variant of the batched run
+// ----------------------------------------------------------------------------
+// The device scratch of pyfpt_run_batch_noalloc: queue counter, instance records, thresholds,
+// staging results and per-workgroup tables.  Every device the library runs on holds its own copy
+// for the life of the process.  In host code this name is only a stand-in for the symbol; the
+// device address comes from hipGetSymbolAddress, once per device (Device::scratch).
+static __device__ __align__(256) unsigned char scratch[PYFPT_NOALLOC_SCRATCH_BYTES];
+
+int noalloc_setup(Device &d) {
+    if (d.scratch) return PYFPT_OK;
+    void *p = nullptr;
+    HIP_TRY(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "hipGetSymbolAddress(scratch)");
+    if (!p) return fail(PYFPT_EDEVICE, "hipGetSymbolAddress(scratch) returned NULL");
+    d.scratch = static_cast<unsigned char *>(p);
+    return PYFPT_OK;
+}
+
+// Sets the calling thread's arena flag for the scope and starts the arena empty.
+struct ArenaScope {
+    ArenaScope() {
+        g_arena_top = 0;
+        g_in_arena = true;
+    }
+    ~ArenaScope() { g_in_arena = false; }
+};
+
+int run_batch_noalloc_impl(const pyfpt_instance *ins, int n_inst, uint64_t seed, pyfpt_result *out,
+                           const pyfpt_options *opt) {
+    if (!ins || !out) return fail(PYFPT_EINVAL, "NULL instance or result array");
+    if (opt && opt->workspace)
+        return fail(PYFPT_EINVAL, "pyfpt_run_batch_noalloc works in its static scratch: workspace must be NULL");
+    if (opt && opt->use_graph)
+        return fail(PYFPT_EINVAL, "pyfpt_run_batch_noalloc does not build graphs (instantiation allocates)");
+    std::lock_guard<std::mutex> lock(g_mu);
+    Device *d = nullptr;
+    int rc;
+    if ((rc = get_device(&d))) return rc;
+    if (d->cus <= 0) return fail(PYFPT_EDEVICE, "no compute units reported");
+    if ((rc = noalloc_setup(*d))) return rc;
+    // the arena is reused: wait until the previous upload from it has been read
+    if (g_arena_upload) HIP_TRY(hipEventSynchronize(g_arena_upload), "hipEventSynchronize");
+    ArenaScope scope;
+    try {
+        Prepared P;
+        if ((rc = prepare(ins, n_inst, P))) return rc;
+        hipStream_t stream = opt ? static_cast<hipStream_t>(opt->stream) : nullptr;
+        LaunchCfg cfg;
+        if (opt) {
+            cfg.block = opt->block;
+            cfg.wg_per_cu = opt->wg_per_cu;
+            cfg.chunk = opt->chunk;
+        }
+        bool lds;
+        resolve_cfg(*d, P, cfg, lds);          // no autotuning: 0 fields take the defaults
+        const int n_wg = d->cus * cfg.wg_per_cu;
+        if (cfg.wg_per_cu < 1 || cfg.wg_per_cu > 64) return fail(PYFPT_EINVAL, "wg_per_cu must be 1..64");
+        const WsMap m = ws_map(P, n_wg);
+        if (m.total > PYFPT_NOALLOC_SCRATCH_BYTES)
+            return fail(PYFPT_ENOMEM,
+                        "pyfpt_run_batch_noalloc needs %zu bytes of scratch for %u table rows on %d workgroups; "
+                        "its static scratch holds %zu (use fewer workgroups per CU, fewer bins or fewer instances)",
+                        m.total, P.lay.n_rows, n_wg, static_cast<size_t>(PYFPT_NOALLOC_SCRATCH_BYTES));
+        if ((rc = run_prepared(*d, P, seed, cfg, opt, stream, d->scratch, PYFPT_NOALLOC_SCRATCH_BYTES, false,
+                               opt ? opt->timing_ms : nullptr, true)))
+            return rc;
+        return copy_out(P, d->scratch, n_wg, out, stream);
+    } catch (const ArenaFull &) {
+        return fail(PYFPT_ENOMEM, "the batch's bookkeeping exceeds the host arena (%zu bytes)", kArenaBytes);
+    }
+}
+
+// ----------------------------------------------------------------------------
 // training of the learned proposal
 // ----------------------------------------------------------------------------
 struct DevBuf {
@@ -811,6 +973,15 @@ int pyfpt_run_batch(const pyfpt_instance *inst, int32_t n_inst, uint64_t seed, p
         return run_batch_impl(inst, n_inst, seed, out, opt);
     } catch (...) {
         return fail(PYFPT_ENOMEM, "host exception (allocation failure)");
+    }
+}
+
+int pyfpt_run_batch_noalloc(const pyfpt_instance *inst, int32_t n_inst, uint64_t seed, pyfpt_result *out,
+                            const pyfpt_options *opt) {
+    try {
+        return run_batch_noalloc_impl(inst, n_inst, seed, out, opt);
+    } catch (...) {
+        return fail(PYFPT_ENOMEM, "host exception");
     }
 }
 
@@ -1357,6 +1528,6 @@ int pyfpt_device_cus(int32_t *cus) {
     return PYFPT_OK;
 }
 
-const char *pyfpt_last_error(void) { return g_err.c_str(); }
+const char *pyfpt_last_error(void) { return g_err; }
 
 }  // extern "C"

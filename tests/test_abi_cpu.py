@@ -168,3 +168,23 @@ def test_training_and_combine_entry_points_reject_bad_input(lib):
     assert L.pyfpt_combine(res, 1, 4, 16, 4, vp(lp), vp(lp), vp(n_used)) == lib.PYFPT_EINVAL      # estimator 4
     assert b"estimator" in L.pyfpt_last_error()
     assert L.pyfpt_combine(res, 0, 4, 16, 0, vp(lp), vp(lp), vp(lp)) == lib.PYFPT_EINVAL          # no results
+
+
+def test_noalloc_entry_point_refuses_workspace_and_graphs(lib):
+    """The allocation-free batch works in its static scratch: a caller workspace or a graph
+    request is refused before any device work."""
+    keep = []
+    arr = (lib.pyfpt_instance * 1)(_instance(lib, keep))
+    res = (lib.pyfpt_result * 1)()
+    opt = lib.pyfpt_options()
+    buf = np.zeros(16, np.uint8)
+    opt.workspace = ctypes.c_void_p(buf.ctypes.data)
+    opt.workspace_bytes = 16
+    assert lib.load().pyfpt_run_batch_noalloc(arr, 1, 0, res, ctypes.byref(opt)) == lib.PYFPT_EINVAL
+    assert b"workspace" in lib.load().pyfpt_last_error()
+    opt = lib.pyfpt_options()
+    opt.use_graph = 1
+    assert lib.load().pyfpt_run_batch_noalloc(arr, 1, 0, res, ctypes.byref(opt)) == lib.PYFPT_EINVAL
+    assert lib.NOALLOC_SCRATCH_BYTES == 64 << 20
+    hdr = open(os.path.join(ROOT, "include", "pyfpt.h")).read()
+    assert "#define PYFPT_NOALLOC_SCRATCH_BYTES (64u << 20)" in hdr
