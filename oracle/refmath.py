@@ -29,6 +29,11 @@ Contents, each citing the passage it follows:
     (Sec. 2.4) and the Gaussian of App. B with gamma = kappa = 0.
   * ``lattice_gaussian_probs`` -- that Gaussian mapped onto the lattice
     N = k dN of the simulation.
+  * ``cumulants_to``, ``saddlepoint_logpdf``, ``saddlepoint_reference`` -- the
+    cumulants of N to any order from the backward equation of the moment
+    generating function, and Daniels' saddle-point density built from them
+    (the resummed form of App. B's cumulant expansion, accurate far beyond
+    the Edgeworth range), mapped onto the lattice with ``lattice_logprobs``.
 """
 from __future__ import annotations
 
@@ -476,6 +481,141 @@ def cumulants(model: Model, biased: bool = False, n_grid: int = 400001, phi=None
     a = solve(n_grid)
     b = solve((n_grid - 1) // 2 + 1)
     return Cumulants(*[ai + (ai - bi) / 3.0 for ai, bi in zip(a, b)])
+
+
+def cumulants_to(model: Model, order: int = 8, biased: bool = False, n_grid: int = 400001, phi=None) -> list:
+    """kappa_1 .. kappa_order of N from phi (default phi_in), by the same hierarchy as `cumulants`
+    taken to any order.  With g = ln E[e^{sN}] the backward equation of the moment generating
+    function (App. A, eq. eq_chracteristic_function_partial_diff_eqn at t = -i s) reads
+    (S^2/2)(g'' + g'^2) + (D+B) g' = -s with g(phi_end) = 0, g'(phi_UV) = 0.  Matching powers of
+    s in g = sum kappa_n s^n/n! gives L kappa_1 = -1 and, for n >= 2,
+    L kappa_n = -(S^2/2) sum_{a=1}^{n-1} binom(n, a) kappa_a' kappa_{n-a}', the cumulants'
+    derivatives being Green's-function integrals with these sources.  Richardson-extrapolated over
+    grids of n and n/2 cells."""
+    phi = model.phi_in if phi is None else phi
+
+    def solve(n):
+        top = _top(model, biased)
+        if model.pot != POT_FLAT and model.phi_end > 0:
+            x = model.phi_end * np.exp(np.linspace(0.0, math.log(top / model.phi_end), n))
+        else:
+            x = np.linspace(model.phi_end, top, n)
+        D, S, B = drift_noise(model, x, biased)
+        psi_p = 2.0 * (D + B) / S ** 2
+        xm = 0.5 * (x[1:] + x[:-1])
+        Dm, Sm, Bm = drift_noise(model, xm, biased)
+        psi_pm = 2.0 * (Dm + Bm) / Sm ** 2
+        J = [_green_derivative(x, psi_p, psi_pm, 2.0 / S ** 2)]
+        for k in range(2, order + 1):
+            src = sum(math.comb(k, a) * J[a - 1] * J[k - a - 1] for a in range(1, k))
+            J.append(_green_derivative(x, psi_p, psi_pm, src))
+        return [float(np.interp(phi, x, _trapz_cum(x, Jk))) for Jk in J]
+
+    a = solve(n_grid)
+    b = solve((n_grid - 1) // 2 + 1)
+    return [ai + (ai - bi) / 3.0 for ai, bi in zip(a, b)]
+
+
+def saddlepoint_root(x: float, K1, K2, s0: float = 0.0) -> float:
+    """The saddle point: the root of K'(s) = x by Newton's method from s0 (K' is increasing, so
+    the root is unique); nan where K'' is not positive along the way."""
+    s = s0
+    for _ in range(200):
+        k2 = K2(s)
+        if not (k2 > 0) or not math.isfinite(k2):
+            return float("nan")
+        ds = (K1(s) - x) / k2
+        s -= ds
+        if abs(ds) <= 1e-15 * max(1.0, abs(s)):
+            break
+    return s
+
+
+def saddlepoint_logpdf_cgf(x: float, K, K1, K2, s0: float = 0.0) -> float:
+    """Daniels' saddle-point density (Ann. Math. Stat. 25, 1954) from a cumulant generating
+    function: log p(x) = K(s) - s x - log sqrt(2 pi K''(s)) at the root of K'(s) = x, found by
+    Newton's method from s0 (K' is increasing, so the root is unique)."""
+    s = s0
+    for _ in range(200):
+        k2 = K2(s)
+        if not (k2 > 0) or not math.isfinite(k2):
+            return float("nan")             # outside the range where the CGF is convex
+        ds = (K1(s) - x) / k2
+        s -= ds
+        if abs(ds) <= 1e-15 * max(1.0, abs(s)):
+            break
+    return K(s) - s * x - 0.5 * math.log(2.0 * math.pi * K2(s))
+
+
+def saddlepoint_logpdf(x: float, kappas) -> float:
+    """The saddle-point density with the cumulant generating function truncated after the given
+    cumulants, K(s) = sum_n kappa_n s^n / n!.  In the drift-dominated and interim regimes the
+    standardised cumulants fall off with their order, so the truncation converges; its effect
+    is the difference between successive orders (`saddlepoint_truncation`).  Near the mean this
+    is the resummed form of the Edgeworth expansion of App. B built from the same cumulants."""
+    kap = [float(k) for k in kappas]
+    fact = [math.factorial(n) for n in range(len(kap) + 1)]
+    K = lambda s: sum(kap[n] * s ** (n + 1) / fact[n + 1] for n in range(len(kap)))
+    K1 = lambda s: sum(kap[n] * s ** n / fact[n] for n in range(len(kap)))
+    K2 = lambda s: sum(kap[n] * s ** (n - 1) / fact[n - 1] for n in range(1, len(kap)))
+    return saddlepoint_logpdf_cgf(x, K, K1, K2, (x - kap[0]) / kap[1])
+
+
+def saddlepoint_term_ratio(x: float, kappas) -> float:
+    """Ratio of the last two terms of the truncated cumulant series at the saddle point of x,
+    kappa_n s / (n kappa_{n-1}) for n = len(kappas): small where the truncation has converged.
+    Where it exceeds 0.35 the truncation error is not bounded by the change from the previous
+    order (for the inverse Gaussian, whose series has a finite radius, it stops being so near
+    half the radius)."""
+    kap = [float(k) for k in kappas]
+    fact = [math.factorial(n) for n in range(len(kap) + 1)]
+    K1 = lambda s: sum(kap[n] * s ** n / fact[n] for n in range(len(kap)))
+    K2 = lambda s: sum(kap[n] * s ** (n - 1) / fact[n - 1] for n in range(1, len(kap)))
+    s = saddlepoint_root(x, K1, K2, (x - kap[0]) / kap[1])
+    n = len(kap)
+    return abs(kap[n - 1] * s / (n * kap[n - 2]))
+
+
+def lattice_logprobs(logpdf, dN: float, edges, eps: float = 0.0, n_gauss: int = 24):
+    """log P(e_j < k dN <= e_{j+1}) for k = ceil((N_c + eps)/dN) when N_c has the log-density
+    `logpdf`: the bin holds the k with K_j < k <= K_{j+1}, K_j = max{k : k dN <= e_j}, i.e.
+    N_c in (K_j dN - eps, K_{j+1} dN - eps], integrated by Gauss-Legendre in log space so that
+    far-tail bins do not underflow (the lattice of `lattice_gaussian_probs` for any density).
+    -inf for a bin that holds no lattice point."""
+    edges = np.asarray(edges, np.float64)
+    Kk = np.floor(edges / dN + 1e-9)
+    Kk = np.where((Kk + 1) * dN <= edges, Kk + 1, Kk)
+    Kk = np.where(Kk * dN > edges, Kk - 1, Kk)
+    xg, wg = np.polynomial.legendre.leggauss(n_gauss)
+    out = np.full(len(edges) - 1, -np.inf)
+    for j, (a, b) in enumerate(zip(Kk[:-1] * dN - eps, Kk[1:] * dN - eps)):
+        if b <= a:
+            continue
+        xs = 0.5 * (a + b) + 0.5 * (b - a) * xg
+        lp = np.array([logpdf(float(x)) for x in xs])
+        top = lp.max()
+        out[j] = top + math.log(0.5 * (b - a) * float(np.sum(wg * np.exp(lp - top))))
+    return out
+
+
+def saddlepoint_reference(model: Model, edges, order: int = 8, n_grid: int = 400001):
+    """Bin-averaged log density of N on the simulation's lattice (k = ceil((N_c + eps)/dN), eps
+    the noise-free Euler-Maruyama lag) from the saddle-point density with `order` cumulants, and
+    its truncation error, twice the change from the previous order:
+    (log P_j, 2 |log P_j(order) - log P_j(order - 1)|).  The error is nan (no reference) in bins
+    whose centre has a last-term ratio above 0.35 (`saddlepoint_term_ratio`)."""
+    kap = cumulants_to(model, order, n_grid=n_grid)
+    _, tau = noise_free_em(model)
+    eps = tau - classical_N(model)
+    edges = np.asarray(edges, np.float64)
+    width = np.log(np.diff(edges))
+    hi = lattice_logprobs(lambda x: saddlepoint_logpdf(x, kap), model.dN, edges, eps) - width
+    lo = lattice_logprobs(lambda x: saddlepoint_logpdf(x, kap[:-1]), model.dN, edges, eps) - width
+    centre = 0.5 * (edges[1:] + edges[:-1]) - eps
+    q = np.array([saddlepoint_term_ratio(float(c), kap) for c in centre])
+    with np.errstate(invalid="ignore"):
+        err = 2.0 * np.abs(hi - lo)
+    return hi, np.where(q <= 0.35, err, np.nan)
 
 
 def hermite_he(n: int, x):
