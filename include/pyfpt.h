@@ -326,10 +326,20 @@ int pyfpt_mlp_forward(const pyfpt_mlp *mlp, double target_N, const float *phi, c
  *                else estimator 0 with its own trust rule (the fallback of Sec. 2.4 taken bin
  *                by bin: with many runs per bin the test resolves the departure from a
  *                lognormal of wide bins and a whole-result gate rejects nearly every result).
+ * Adding PYFPT_COMBINE_NO_EXTRAPOLATION to the estimator also requires n_j >= exp(s_j^2/2) of a
+ * lognormal estimate (s_j^2 the unbiased variance of ln w in the bin): its value
+ * exp(<ln w> + s^2/2) comes from ln w about s standard deviations above the mean, which n draws
+ * reach only if s <= sqrt(2 ln n); beyond that the estimate extrapolates the normal law of
+ * ln w into a range no run has sampled (an addition to the paper's gate, which cannot test
+ * that range).
+ * Where several results contribute to a bin and scatter more than their errors allow
+ * (chi^2 = sum_i (y_i - y_bar)^2 / e_i^2 > n_used - 1), err_log is scaled by Birge's ratio
+ * sqrt(chi^2 / (n_used - 1)).
  * res: n_res results (host or device buffers, as each one's on_device says).  Outputs (host,
  * n_bins each): log_p (NaN where nothing contributes), err_log (standard error of log P),
  * n_used (contributing results).  Host arithmetic; EINVAL for bad arguments.
  */
+#define PYFPT_COMBINE_NO_EXTRAPOLATION 16
 int pyfpt_combine(const pyfpt_result *res, int32_t n_res, int32_t n_bins, int32_t n_sub, int32_t estimator,
                   double *log_p, double *err_log, int32_t *n_used);
 

@@ -419,6 +419,9 @@ class Histogram:
             return np.exp(2 * self.lse_w[:B] - self.lse_w2[:B])
 
 
+COMBINE_NO_EXTRAPOLATION = 16
+
+
 def combine(hists, estimator: int = 2):
     """Multi-bias reconstruction (Sec. 3.2, 3.3): per bin, the inverse-variance weighted mean of
     log P_hat over the histograms whose estimate is trusted there.  estimator 0: naive P_hat,
@@ -427,13 +430,23 @@ def combine(hists, estimator: int = 2):
     lognormal estimator for a histogram that passes the gate in every bin with a p-value, else
     the naive one; 3: bin by bin, the lognormal estimate where that bin passes the gate
     (n_j >= 8, p >= 0.005), else the naive one under its own rule -- the fallback of Sec. 2.4
-    taken per bin.  Returns (log_p, err_log, n_used)."""
+    taken per bin.
+
+    Adding COMBINE_NO_EXTRAPOLATION (16) also requires n_j >= exp(s_j^2 / 2) of a lognormal
+    estimate: exp(<ln w> + s^2/2) draws its value from ln w near <ln w> + s^2, i.e. s standard
+    deviations above the mean, which n draws reach only if s <= sqrt(2 ln n).
+
+    Where several estimates contribute to a bin and scatter more than their errors allow
+    (chi^2 = sum w_i (y_i - y_bar)^2 above n - 1), the error of the mean is scaled by
+    sqrt(chi^2 / (n - 1)) (Birge's ratio).  Returns (log_p, err_log, n_used)."""
+    kind = estimator & ~COMBINE_NO_EXTRAPOLATION
+    if kind not in (0, 1, 2, 3):
+        raise ValueError("estimator must be 0..3, optionally + COMBINE_NO_EXTRAPOLATION")
+    strict = bool(estimator & COMBINE_NO_EXTRAPOLATION)
     B = len(hists[0].edges) - 1
-    sw = np.zeros(B)
-    swy = np.zeros(B)
-    used = np.zeros(B, np.int32)
+    ys, ws = [], []
     for h in hists:
-        est = estimator
+        est = kind
         pv = h.normal_p[:B]
         if est == 2:
             est = 1 if not np.any(np.isfinite(pv) & (pv < 0.005)) else 0
@@ -444,8 +457,11 @@ def combine(hists, estimator: int = 2):
             ok0 = (n > 400) & (n > np.exp(h.m2_lnw[:B]))
         y1, _, hi = h.lognormal()
         e1 = np.log1p(hi)
-        with np.errstate(invalid="ignore"):
+        with np.errstate(invalid="ignore", over="ignore", divide="ignore"):
             ok1 = (n >= 8) & np.isfinite(pv) & (pv >= 0.005)
+            if strict:
+                s2 = h.m2_lnw[:B] * n / (n - 1)
+                ok1 &= n >= np.exp(0.5 * s2)
         if est == 0:
             y, e, ok = y0, e0, ok0
         elif est == 1:
@@ -454,12 +470,17 @@ def combine(hists, estimator: int = 2):
             y, e, ok = np.where(ok1, y1, y0), np.where(ok1, e1, e0), ok1 | ok0
         with np.errstate(invalid="ignore"):
             ok &= np.isfinite(y) & np.isfinite(e) & (e > 0)
-        w = np.where(ok, 1.0 / np.where(ok, e, 1.0) ** 2, 0.0)
-        sw += w
-        swy += np.where(ok, w * np.where(ok, y, 0.0), 0.0)
-        used += ok
+        ws.append(np.where(ok, 1.0 / np.where(ok, e, 1.0) ** 2, 0.0))
+        ys.append(np.where(ok, y, 0.0))
+    W = np.array(ws)
+    Y = np.array(ys)
+    used = np.sum(W > 0, axis=0).astype(np.int32)
+    sw = W.sum(axis=0)
     with np.errstate(invalid="ignore", divide="ignore"):
-        return np.where(used > 0, swy / sw, np.nan), np.where(used > 0, 1.0 / np.sqrt(sw), np.nan), used
+        mean = np.sum(W * Y, axis=0) / sw
+        chi2 = np.sum(W * (Y - mean[None, :]) ** 2, axis=0)
+        birge = np.where(used > 1, np.sqrt(np.maximum(1.0, chi2 / np.maximum(used - 1, 1))), 1.0)
+        return np.where(used > 0, mean, np.nan), np.where(used > 0, birge / np.sqrt(sw), np.nan), used
 
 
 def bin_rows(k: np.ndarray, status: np.ndarray, dN: float, edges: np.ndarray) -> np.ndarray:

@@ -331,9 +331,14 @@ def device_cus() -> int:
     return int(n.value)
 
 
+COMBINE_NO_EXTRAPOLATION = 16     # PYFPT_COMBINE_NO_EXTRAPOLATION
+
+
 def combine(results, estimator: int = 2):
     """Multi-bias reconstruction (pyfpt_combine): per-bin inverse-variance combination in
-    log P of results sharing the same bins.  Returns (log_p, err_log, n_used)."""
+    log P of results sharing the same bins, errors scaled by Birge's ratio where contributors
+    disagree; estimator + COMBINE_NO_EXTRAPOLATION adds the lognormal rule n_j >= exp(s^2/2).
+    Returns (log_p, err_log, n_used)."""
     n = len(results)
     B = results[0].n_bins
     arr = (L.pyfpt_result * n)()

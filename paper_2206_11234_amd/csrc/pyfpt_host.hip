@@ -1054,13 +1054,17 @@ int pyfpt_mlp_forward(const pyfpt_mlp *mlp, double target_N, const float *phi, c
 static int pyfpt_combine_impl(const pyfpt_result *res, int32_t n_res, int32_t n_bins, int32_t n_sub, int32_t estimator,
                   double *log_p, double *err_log, int32_t *n_used) {
     if (!res || !log_p || !err_log || !n_used || n_res < 1) return fail(PYFPT_EINVAL, "NULL argument or n_res < 1");
-    if (estimator < 0 || estimator > 3) return fail(PYFPT_EINVAL, "estimator must be 0, 1, 2 or 3");
+    const bool strict = (estimator & PYFPT_COMBINE_NO_EXTRAPOLATION) != 0;
+    const int32_t kind = estimator & ~PYFPT_COMBINE_NO_EXTRAPOLATION;
+    if (kind < 0 || kind > 3)
+        return fail(PYFPT_EINVAL, "estimator must be 0, 1, 2 or 3, optionally + PYFPT_COMBINE_NO_EXTRAPOLATION");
     if (n_bins < 1) return fail(PYFPT_EINVAL, "n_bins must be >= 1");
     if (n_sub == 0) n_sub = kDefaultNsub;
     if (n_sub < 2 || n_sub > 64) return fail(PYFPT_EINVAL, "n_sub must be 0 or 2..64");
     const ResultLayout L = result_layout(static_cast<uint32_t>(n_bins), static_cast<uint32_t>(n_sub));
     const uint32_t B = static_cast<uint32_t>(n_bins);
-    std::vector<double> sw(B, 0.0), swy(B, 0.0);
+    // per (result, bin): the estimate y and its weight 1/e^2 (0 where not trusted)
+    std::vector<double> ys(static_cast<size_t>(n_res) * B, 0.0), ws(static_cast<size_t>(n_res) * B, 0.0);
     std::fill(n_used, n_used + B, 0);
     std::vector<uint64_t> cbuf;
     std::vector<double> vbuf;
@@ -1076,7 +1080,7 @@ static int pyfpt_combine_impl(const pyfpt_result *res, int32_t n_res, int32_t n_
             C = cbuf.data();
             V = vbuf.data();
         }
-        int est = estimator;
+        int est = kind;
         if (est == 2) {
             bool gate = true;
             for (uint32_t j = 0; j < B; ++j) {
@@ -1088,24 +1092,44 @@ static int pyfpt_combine_impl(const pyfpt_result *res, int32_t n_res, int32_t n_
         for (uint32_t j = 0; j < B; ++j) {
             const double n = static_cast<double>(C[L.count + j]);
             // naive estimate, trusted when n > 400 and n > exp(var ln w); lognormal estimate,
-            // trusted when the bin passes the normality gate
+            // trusted when the bin passes the normality gate (and, with the no-extrapolation
+            // rule, when n >= exp(s^2/2): the mean of w rests on ln w about s standard deviations
+            // above its mean, which n draws reach only if s <= sqrt(2 ln n))
             const double p = V[L.normal_p + j];
-            const bool gate = n >= 8.0 && std::isfinite(p) && p >= 0.005;
+            bool gate = n >= 8.0 && std::isfinite(p) && p >= 0.005;
+            if (strict && gate) gate = n >= std::exp(0.5 * V[L.m2_lnw + j] * n / (n - 1.0));
             const bool naive_ok = n > 400.0 && n > std::exp(V[L.m2_lnw + j]);
             const bool use_ln = est == 1 || (est == 3 && gate);
             const double y = use_ln ? V[L.log_p_ln + j] : V[L.log_p + j];
             const double e = use_ln ? std::log1p(V[L.rel_err_ln_hi + j]) : V[L.rel_err_jk + j];
             const bool ok = est == 0 ? naive_ok : (est == 1 ? gate : gate || naive_ok);
             if (!ok || !std::isfinite(y) || !std::isfinite(e) || !(e > 0)) continue;
-            const double w = 1.0 / (e * e);
-            sw[j] += w;
-            swy[j] += w * y;
+            ys[static_cast<size_t>(i) * B + j] = y;
+            ws[static_cast<size_t>(i) * B + j] = 1.0 / (e * e);
             n_used[j] += 1;
         }
     }
+    // inverse-variance mean; where the contributors scatter more than their errors allow
+    // (chi^2 > n - 1), the error is scaled by Birge's ratio sqrt(chi^2 / (n - 1))
     for (uint32_t j = 0; j < B; ++j) {
-        log_p[j] = n_used[j] ? swy[j] / sw[j] : NAN;
-        err_log[j] = n_used[j] ? 1.0 / std::sqrt(sw[j]) : NAN;
+        if (!n_used[j]) {
+            log_p[j] = err_log[j] = NAN;
+            continue;
+        }
+        double sw = 0.0, swy = 0.0;
+        for (int32_t i = 0; i < n_res; ++i) {
+            sw += ws[static_cast<size_t>(i) * B + j];
+            swy += ws[static_cast<size_t>(i) * B + j] * ys[static_cast<size_t>(i) * B + j];
+        }
+        const double mean = swy / sw;
+        double chi2 = 0.0;
+        for (int32_t i = 0; i < n_res; ++i) {
+            const double d = ys[static_cast<size_t>(i) * B + j] - mean;
+            chi2 += ws[static_cast<size_t>(i) * B + j] * d * d;
+        }
+        const double birge = n_used[j] > 1 ? std::sqrt(std::max(1.0, chi2 / (n_used[j] - 1))) : 1.0;
+        log_p[j] = mean;
+        err_log[j] = birge / std::sqrt(sw);
     }
     return PYFPT_OK;
 }
