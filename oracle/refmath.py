@@ -364,6 +364,229 @@ def sl_modes(model: Model, n_modes: int = 3, lam_max: float | None = None, n_sca
     return Modes(np.array(lams), np.array(amps))
 
 
+def _prufer_shoot(model: Model, lam: float, rtol: float = 1e-12):
+    """The Sturm-Liouville problem of `sl_modes` in Pruefer form, for drift-dominated cases where
+    psi, psi' and rho span more than the binary64 range.  With psi = r sin(theta),
+    psi' = r cos(theta), psi(phi_end) = 0, psi'(phi_end) = 1:
+      theta' = cos^2 + (2/S^2)(D sin cos + Lambda sin^2),
+      eta'   = (log r + Psi)' = sin cos - (2 Lambda/S^2) sin cos + (2D/S^2) sin^2,
+      Psi'   = 2D/S^2,
+      and the variation d theta/d Lambda along the path (its linearised equation).
+    Returns the solution of (theta, eta, Psi, d theta/d Lambda) (a stiff system: LSODA, which
+    switches to a stiff method where needed, with the implicit Runge-Kutta method as fallback)."""
+    ds2 = _scalar_drift_s2(model)
+
+    def rhs(x, y):
+        th, _, _, thl = y
+        D, S2 = ds2(x)
+        sn, cs = math.sin(th), math.cos(th)
+        g = 2.0 / S2
+        a = -2.0 * sn * cs + g * (D * (cs * cs - sn * sn) + 2.0 * lam * sn * cs)
+        return [cs * cs + g * (D * sn * cs + lam * sn * sn), sn * cs - g * lam * sn * cs + g * D * sn * sn,
+                g * D, a * thl + g * sn * sn]
+
+    def jac(x, y):
+        th, _, _, thl = y
+        D, S2 = ds2(x)
+        sn, cs = math.sin(th), math.cos(th)
+        g = 2.0 / S2
+        c2 = cs * cs - sn * sn
+        a = -2.0 * sn * cs + g * (D * c2 + 2.0 * lam * sn * cs)
+        da = -2.0 * c2 + g * (-4.0 * D * sn * cs + 2.0 * lam * c2)
+        return [[a, 0, 0, 0], [c2 - g * lam * c2 + 2.0 * g * D * sn * cs, 0, 0, 0], [0, 0, 0, 0],
+                [da * thl + 2.0 * g * sn * cs, 0, 0, a]]
+
+    sol = integrate.solve_ivp(rhs, (model.phi_end, model.phi_uv), [0.0, 0.0, 0.0, 0.0], method="LSODA",
+                              rtol=rtol, atol=1e-14, dense_output=True)
+    if sol.success and np.all(np.isfinite(sol.y[:, -1])):
+        return sol
+    return integrate.solve_ivp(rhs, (model.phi_end, model.phi_uv), [0.0, 0.0, 0.0, 0.0], method="Radau",
+                               rtol=rtol, atol=1e-14, jac=jac, dense_output=True)
+
+
+def sl_modes_prufer(model: Model, n_modes: int, lam_lo: float, lam_hi: float, n_scan: int = 40) -> Modes:
+    """The first n_modes (Lambda_n, a_n) with Lambda_n in [lam_lo, lam_hi], from the Pruefer form.
+    Mode n has theta(phi_UV) = pi/2 + n pi (psi'(phi_UV) = 0 with n interior zeros).  The
+    amplitude uses the Sturm-Liouville identities int rho psi = p(phi_end) psi'(phi_end)/Lambda
+    (integrate (p psi')' = -Lambda rho psi) and int rho psi^2 = p r^2 d theta/d Lambda at phi_UV
+    (the Lambda-derivative of the same equation), p = e^Psi, so that
+      a_n = Lambda c_n psi(phi_in) = sin(theta_in) exp(eta_in - Psi_in - 2 eta_UV + Psi_UV) / (d theta/d Lambda)_UV
+    with every exponent formed before exponentiation."""
+    if not np.isfinite(model.phi_uv):
+        raise ValueError("the pole expansion needs a finite reflecting wall")
+    grid = np.linspace(lam_lo, lam_hi, n_scan)
+    th = np.array([_prufer_shoot(model, l, 1e-9).y[0, -1] for l in grid])
+    lams, amps = [], []
+    for n in range(64):
+        tgt = math.pi / 2 + n * math.pi
+        hit = np.nonzero((th[:-1] - tgt) * (th[1:] - tgt) <= 0)[0]
+        if not hit.size:
+            continue
+        i = hit[0]
+        # Newton's method on theta(phi_UV; Lambda) with the carried derivative d theta/d Lambda,
+        # kept inside the bracket (bisection where a step would leave it)
+        lo, hi = grid[i], grid[i + 1]
+        lam = 0.5 * (lo + hi)
+        for _ in range(60):
+            sol = _prufer_shoot(model, lam)
+            f = sol.y[0, -1] - tgt
+            if f < 0:
+                lo = lam
+            else:
+                hi = lam
+            step = f / sol.y[3, -1]
+            new = lam - step
+            if not lo < new < hi:
+                new = 0.5 * (lo + hi)
+            if abs(new - lam) <= 1e-14 * max(1.0, abs(lam)):
+                lam = new
+                break
+            lam = new
+        sol = _prufer_shoot(model, lam)
+        thb, etab, Psib, thlb = sol.y[:, -1]
+        thi, etai, Psii, _ = sol.y[:, -1] if model.phi_in >= model.phi_uv else sol.sol(model.phi_in)
+        lams.append(lam)
+        amps.append(math.sin(thi) * math.exp(etai - Psii - 2.0 * etab + Psib) / thlb)
+        if len(lams) == n_modes:
+            break
+    return Modes(np.array(lams), np.array(amps))
+
+
+def cgf_walled(model: Model, s: float, order: int = 4, rtol: float = 1e-10, method: str = "Radau"):
+    """K(s) = ln E[e^{sN}] of the first-passage time from phi_in and its first `order` derivatives
+    in s, without truncation, for a reflecting wall at phi_UV (finite for s below the slowest decay
+    rate Lambda_0).  y = d/dphi ln E[e^{sN}] obeys the Riccati form of the backward equation
+    (App. A's equation for the characteristic function at t = -i s),
+      (S^2/2)(y' + y^2) + D y = -s,  y(phi_UV) = 0,
+    integrated from the wall down to phi_end (the direction in which it is stable), and
+    K^(n)(s) = int_{phi_end}^{phi_in} d^n y / ds^n, the s-derivatives obeying the differentiated
+    equations.  Returns [K, K', ..., K^(order)]."""
+    if not np.isfinite(model.phi_uv):
+        raise ValueError("cgf_walled needs a finite reflecting wall")
+    ds2 = _scalar_drift_s2(model)
+    n1 = order + 1
+    binom = [[math.comb(n, k) for k in range(n + 1)] for n in range(n1)]
+
+    def rhs(x, Y):
+        D, S2 = ds2(x)
+        g = 2.0 / S2
+        y = Y[:n1]
+        out = np.empty(2 * n1)
+        for n in range(n1):
+            sq = 0.0
+            for k in range(n + 1):
+                sq += binom[n][k] * y[k] * y[n - k]
+            out[n] = -sq - g * D * y[n] - (g * s if n == 0 else (g if n == 1 else 0.0))
+        out[n1:] = y
+        return out
+
+    def jac(x, Y):
+        D, S2 = ds2(x)
+        gD = 2.0 * D / S2
+        J = np.zeros((2 * n1, 2 * n1))
+        for n in range(n1):
+            for k in range(n + 1):
+                J[n, k] -= 2.0 * binom[n][k] * Y[n - k]
+            J[n, n] -= gD
+            J[n1 + n, n] = 1.0
+        return J
+
+    def blow_up(x, Y):              # beyond the slowest decay rate y diverges: stop before overflow
+        return 1e100 - abs(Y[0]) if math.isfinite(Y[0]) else -1.0
+    blow_up.terminal = True
+
+    with np.errstate(over="ignore", invalid="ignore"):
+        extra = {"jac": jac} if method in ("Radau", "BDF") else {}
+        sol = integrate.solve_ivp(rhs, (model.phi_uv, model.phi_end), np.zeros(2 * n1), method=method,
+                                  rtol=rtol, atol=1e-14, dense_output=True, events=blow_up, **extra)
+    if not sol.success or sol.status == 1 or not np.all(np.isfinite(sol.y[:, -1])):
+        raise ArithmeticError(f"cgf_walled: integration failed at s = {s}: {sol.message}")
+    i_end = sol.y[n1:, -1]
+    i_in = np.zeros(n1) if model.phi_in >= model.phi_uv else sol.sol(model.phi_in)[n1:]
+    return [float(i_in[n] - i_end[n]) for n in range(n1)]
+
+
+def saddlepoint_walled_reference(model: Model, edges, n_s: int = 120):
+    """Bin-averaged log density of N on the simulation's lattice from Daniels' saddle-point density
+    with the exact cumulant generating function of `cgf_walled` (no truncation of cumulants), with
+    Daniels' second-order factor 1 + lambda_4/8 - 5 lambda_3^2/24 (lambda_k = K^(k)/K''^(k/2)), and
+    the size of that factor squared as the reference's error:
+    (log P_j, |log(1 + correction)|^2 at the bin centre).  The saddle points are tabulated over
+    s up to just below the slowest decay rate (where K' -> infinity) and log p(x) is interpolated
+    in x."""
+    edges = np.asarray(edges, np.float64)
+    _, tau = noise_free_em(model)
+    eps = tau - classical_N(model)
+    x_lo, x_hi = edges[0] - eps, edges[-1] - eps
+    k0 = cgf_walled(model, 0.0, 2)
+    # lower end of the s range: K'(s_lo) <= x_lo (bisected below when x_lo lies above the mean)
+    if k0[1] > x_lo:
+        s_lo = -1.0 / k0[2] * 0.5
+        while cgf_walled(model, s_lo, 1)[1] > x_lo:
+            s_lo *= 2.0
+    else:
+        s_lo = None
+    # upper end: bracket K'(s) = x_hi, doubling toward the divergence (probed with the implicit
+    # Runge-Kutta method, which stops quietly where y diverges)
+    def probe(sv):
+        try:
+            v = cgf_walled(model, sv, 1, rtol=1e-7)[1]
+        except ArithmeticError:
+            return np.inf
+        return v if np.isfinite(v) else np.inf
+
+    s_a, s_b = 0.0, 1.0 / k0[2]
+    while probe(s_b) < x_hi:
+        s_a, s_b = s_b, 2.0 * s_b
+    while s_b - s_a > 1e-5 * max(1.0, abs(s_b)):
+        mid = 0.5 * (s_a + s_b)
+        if probe(mid) < x_hi:
+            s_a = mid
+        else:
+            s_b = mid
+    s_hi = s_b if np.isfinite(probe(s_b)) else s_a
+    if s_lo is None:
+        a, b = 0.0, s_hi
+        while b - a > 1e-5 * max(1.0, abs(b)):
+            mid = 0.5 * (a + b)
+            if probe(mid) <= x_lo:
+                a = mid
+            else:
+                b = mid
+        s_lo = a
+    # grid: uniform in s below 0, denser toward s_hi above it
+    u = np.linspace(0.0, 1.0, n_s)
+    s0 = max(s_lo, 0.0)
+    s_grid = s0 + (s_hi - s0) * (1.0 - (1.0 - u) ** 3)
+    if s_lo < 0:
+        s_grid = np.concatenate([np.linspace(s_lo, 0.0, n_s // 4, endpoint=False), s_grid])
+    xs, lp, cr = [], [], []
+    for sv in s_grid:
+        try:
+            K = cgf_walled(model, float(sv), 4, method="LSODA")
+            if not (K[2] > 0):
+                raise ArithmeticError
+        except ArithmeticError:
+            K = cgf_walled(model, float(sv), 4)
+        if not (K[2] > 0):
+            raise ArithmeticError(f"saddlepoint_walled_reference: K''({sv}) = {K[2]}")
+        lam3 = K[3] / K[2] ** 1.5
+        lam4 = K[4] / K[2] ** 2
+        corr = math.log1p(lam4 / 8.0 - 5.0 * lam3 * lam3 / 24.0)
+        xs.append(K[1])
+        lp.append(K[0] - sv * K[1] - 0.5 * math.log(2.0 * math.pi * K[2]) + corr)
+        cr.append(corr)
+    xs, lp, cr = np.array(xs), np.array(lp), np.array(cr)
+    order = np.argsort(xs)
+    xs, lp, cr = xs[order], lp[order], cr[order]
+    from scipy.interpolate import CubicSpline
+    spl = CubicSpline(xs, lp)
+    width = np.log(np.diff(edges))
+    out = lattice_logprobs(lambda x: float(spl(x)), model.dN, edges, eps) - width
+    centre = 0.5 * (edges[1:] + edges[:-1]) - eps
+    return out, np.interp(centre, xs, cr) ** 2
+
+
 # --------------------------------------------------------------------------
 # The zero-variance proposal for a window of first-passage times.
 #

@@ -99,3 +99,39 @@ def assert_dump_matches(dump, tr):
     lw_ok = np.abs(dump.lw[:n] - tr.lw) <= 1e-5 * np.maximum(1.0, np.abs(tr.lw))
     assert np.all(lw_ok), ("lw beyond 1e-5", np.nonzero(~lw_ok)[0][:10])
     assert np.array_equal(dump.lw[:n], tr.lw), "lw not bit-identical"
+
+
+def check_z(z, dof=None, label="", p_min=1e-3):
+    """Agreement of estimates with a reference, given z = (estimate - reference) / error per bin.
+
+    dof: degrees of freedom of the errors when they are estimated from few groups (jackknife
+    over J subsets: J - 1); each z is then mapped to a standard normal deviate through Student's
+    t distribution before the checks.  Passes when
+      (1) at most 1 % of the bins lie beyond 3 sigma -- or, for sets under 100 bins, no more
+          than Gaussian errors give with probability 1 - p_min (binomial tail at the rate
+          2 Phi(-3) = 0.27 %), and
+      (2) chi^2 = sum z^2 has a p-value of at least p_min under n degrees of freedom.
+    Returns the summary it prints."""
+    from scipy import stats
+    z = np.asarray(z, np.float64)
+    assert z.size > 0 and np.all(np.isfinite(z)), (label, z)
+    if dof is not None:
+        z = stats.norm.ppf(np.clip(stats.t.cdf(z, dof), 1e-300, 1.0 - 1e-16))
+    n = z.size
+    beyond = int(np.sum(np.abs(z) > 3.0))
+    rate = 2.0 * stats.norm.sf(3.0)
+    p_beyond = float(stats.binom.sf(beyond - 1, n, rate)) if beyond else 1.0
+    chi2 = float(np.sum(z * z))
+    p_chi2 = float(stats.chi2.sf(chi2, n))
+    s = dict(label=label, n=n, beyond_3sigma=beyond, frac_beyond=beyond / n, p_beyond=p_beyond,
+             chi2_per_bin=chi2 / n, p_chi2=p_chi2, max_abs=float(np.max(np.abs(z))), mean=float(np.mean(z)))
+    print("[z] " + " ".join(f"{k}={v:.4g}" if isinstance(v, float) else f"{k}={v}" for k, v in s.items()), flush=True)
+    assert beyond <= 0.01 * n or (n < 100 and p_beyond >= p_min), s
+    assert p_chi2 >= p_min, s
+    return s
+
+
+def z_two_sided(d, err_lo, err_hi):
+    """z of a log-space difference d = log(estimate) - log(reference) with asymmetric errors:
+    the upper error where the estimate lies above the reference, the lower one below."""
+    return np.where(d > 0, d / err_lo, d / err_hi)

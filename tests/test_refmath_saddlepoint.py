@@ -133,3 +133,89 @@ def test_saddlepoint_reference_normalises_and_has_the_drift_cumulants():
     mean = np.trapezoid(p * x, x) / Z
     var = np.trapezoid(p * (x - mean) ** 2, x) / Z
     assert abs(mean - kap[0]) < 1e-5 * sd and abs(var / kap[1] - 1) < 1e-6
+
+
+# ---------------------------------------------------------------------------------------------
+# The exact cumulant generating function with a reflecting wall (Riccati form of the backward
+# equation), the saddle-point reference built on it, and the Pruefer form of the pole expansion.
+# ---------------------------------------------------------------------------------------------
+def test_walled_cgf_matches_the_flat_well_closed_form():
+    """Brownian motion from x, absorbing at 0, reflecting at L (constant V):
+    E[e^{sT}] = cos(k (L - x)) / cos(k L) with k = sqrt(2 s)/S (cosh for s < 0); its logarithm
+    and the first two s-derivatives (central differences of the closed form) are reproduced."""
+    L, x = 1.5, 1.0
+    m = O.Model(pot=O.POT_FLAT, V0=1.0, phi_in=x, phi_end=0.0, phi_uv=L)
+    S = math.sqrt(1 / 3) / (2 * math.pi)
+
+    def logM(s):
+        if s > 0:
+            k = math.sqrt(2 * s) / S
+            return math.log(math.cos(k * (L - x)) / math.cos(k * L))
+        k = math.sqrt(-2 * s) / S
+        return math.log(math.cosh(k * (L - x)) / math.cosh(k * L))
+    def dlogM(s):           # d/ds, with dk/ds = k/(2s) on both sides of s = 0
+        if s > 0:
+            k = math.sqrt(2 * s) / S
+            return k / (2 * s) * (L * math.tan(k * L) - (L - x) * math.tan(k * (L - x)))
+        k = math.sqrt(-2 * s) / S
+        return k / (2 * s) * ((L - x) * math.tanh(k * (L - x)) - L * math.tanh(k * L))
+    for s in (-0.05, -0.002, 0.0015, 0.004):
+        K = R.cgf_walled(m, s, 2)
+        h = 1e-6 * abs(s)
+        d2 = (dlogM(s + h) - dlogM(s - h)) / (2 * h)
+        assert abs(K[0] - logM(s)) < 1e-9 * max(1, abs(logM(s))), (s, K[0], logM(s))
+        assert abs(K[1] - dlogM(s)) < 1e-8 * abs(dlogM(s)), (s, K[1], dlogM(s))
+        assert abs(K[2] - d2) < 1e-5 * abs(d2), (s, K[2], d2)
+
+
+def test_walled_cgf_derivatives_at_zero_are_the_cumulants():
+    """The interim-mass case (m = 0.1, phi_in = phi_UV = sqrt 42): the s-derivatives of the exact
+    generating function at s = 0 equal the cumulants from the Green's-function hierarchy, two
+    independent routes through the same backward equation."""
+    phi = math.sqrt(42.0)
+    m = O.Model(m=0.1, phi_in=phi, phi_uv=phi)
+    K = R.cgf_walled(m, 0.0, 4)
+    kap = R.cumulants_to(m, 4, n_grid=200001)
+    assert abs(K[0]) < 1e-12
+    for n in range(4):
+        assert abs(K[n + 1] - kap[n]) < 1e-6 * abs(kap[n]), (n, K[n + 1], kap[n])
+
+
+@pytest.fixture(scope="module")
+def diffusion_modes():
+    """Pole expansion of the diffusion-dominated workload (m = 1, phi_in = 6, wall at 8) by the
+    direct shooting solver (pinned against the 1F1 residues and the finite-difference solve)."""
+    return R.sl_modes(O.Model(m=1.0, phi_in=6.0, phi_uv=8.0), 3, lam_max=4.0, n_scan=160)
+
+
+def test_walled_saddlepoint_reference_matches_the_pole_expansion_in_the_far_tail(diffusion_modes):
+    """The diffusion-dominated workload (m = 1, phi_in = 6, wall at 8): far in the tail a few poles
+    describe P(N) (App. A); there the saddle-point reference with the exact generating function
+    agrees with the Sturm-Liouville pole expansion (pinned by the 1F1 residues and the
+    finite-difference eigen-solve) to within its stated error plus 0.5 %."""
+    m = O.Model(m=1.0, phi_in=6.0, phi_uv=8.0, dN=1e-3)
+    edges = np.array([80.0, 80.5, 120.0, 120.5, 180.0, 180.5, 260.0, 260.5])
+    ref, err = R.saddlepoint_walled_reference(m, edges, n_s=24)
+    modes = diffusion_modes
+    _, tau = R.noise_free_em(m)
+    eps = tau - R.classical_N(m)
+    for j in (0, 2, 4, 6):
+        N = np.linspace(edges[j], edges[j + 1], 65) - eps
+        pole = np.trapezoid(np.sum(modes.amp[None, :] * np.exp(-modes.lam[None, :] * N[:, None]), axis=1), N) / 0.5
+        assert abs(ref[j] - math.log(pole)) < err[j] + 5e-3, (edges[j], ref[j], math.log(pole), err[j])
+
+
+def test_pruefer_modes_match_closed_forms_and_the_shooting_solver(diffusion_modes):
+    """The Pruefer form of the Sturm-Liouville problem reproduces the flat well's sine series
+    (Lambda_n = (2n+1)^2 pi^2 S^2 / (8 L^2), a_n = Lambda_n 4/((2n+1) pi) sin((2n+1) pi x/(2L)))
+    and the direct shooting of the diffusion-dominated case, amplitudes included."""
+    mf = O.Model(pot=O.POT_FLAT, V0=1.0, phi_in=1.0, phi_end=0.0, phi_uv=1.5)
+    S = math.sqrt(1 / 3) / (2 * math.pi)
+    md = R.sl_modes_prufer(mf, 3, 0.001, 0.12, n_scan=12)
+    for n in range(3):
+        lam = (2 * n + 1) ** 2 * math.pi ** 2 * S ** 2 / (8 * 1.5 ** 2)
+        amp = lam * 4 / ((2 * n + 1) * math.pi) * math.sin((2 * n + 1) * math.pi / 3)
+        assert abs(md.lam[n] / lam - 1) < 1e-9 and abs(md.amp[n] - amp) < 1e-8 * max(1e-3, abs(amp))
+    m = O.Model(m=1.0, phi_in=6.0, phi_uv=8.0)
+    a, b = R.sl_modes_prufer(m, 3, 0.05, 1.2, n_scan=12), diffusion_modes
+    assert np.allclose(a.lam, b.lam, rtol=1e-9) and np.allclose(a.amp, b.amp, rtol=1e-6)
