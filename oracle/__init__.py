@@ -34,6 +34,8 @@ POT_QUADRATIC, POT_QUADRATIC_BUMP, POT_FLAT = 0, 1, 2
 BIAS_NONE, BIAS_NOISE_SCALED, BIAS_POWER, BIAS_MLP = 0, 1, 2, 3
 ST_ENDED, ST_CENSORED, ST_ESCAPED = 1, 2, 3
 MODE_F32, MODE_F64 = 0, 1
+# the binary32 step of MODE_F32 with ln w summed in binary32 (Kahan-compensated, or plainly)
+MODE_F32_KAHAN, MODE_F32_SUM = 2, 3
 
 
 class _Params(ctypes.Structure):

@@ -103,6 +103,8 @@ static uint32_t f32_to_bits(float f) { uint32_t b; memcpy(&b, &f, 4); return b; 
 /* y <- y (2 - x y), written y <- fma(y, fma(-x, y, 1), y), three times */
 /* from the exponent-negating seed bits(0x7EF311C3 - bits(x)) (relative */
 /* error below 5.1%, so 3 steps reach the binary32 rounding level).     */
+/* The bit-subtraction seed is J. Blinn's ("Floating-point tricks",     */
+/* IEEE CG&A 17(4), 1997); 0x7EF311C3 is a published tuning of it.      */
 /* ------------------------------------------------------------------ */
 float oracle_recip_f32(float x)
 {
@@ -119,7 +121,8 @@ float oracle_recip_f32(float x)
 /* by Newton-Raphson y <- y (3 - x y^2)/2, written                      */
 /* y <- fma(y, fma(-x/2, y*y, 1/2), y), three times from the seed       */
 /* bits(0x5F3759DF - (bits(x) >> 1)) (relative error below 3.5%), then  */
-/* sqrt x = x y.                                                        */
+/* sqrt x = x y.  The seed constant is the Quake III Arena one (1999),   */
+/* analysed by C. Lomont, "Fast inverse square root" (2003).            */
 /* ------------------------------------------------------------------ */
 float oracle_sqrt_f32(float x)
 {
@@ -280,7 +283,10 @@ void oracle_normals_f64(uint64_t seed, uint32_t stream, uint64_t t, uint32_t j, 
 enum { POT_QUADRATIC = 0, POT_QUADRATIC_BUMP = 1, POT_FLAT = 2 };
 enum { BIAS_NONE = 0, BIAS_NOISE_SCALED = 1, BIAS_POWER = 2, BIAS_MLP = 3 };
 enum { ST_RUNNING = 0, ST_ENDED = 1, ST_CENSORED = 2, ST_ESCAPED = 3 };
-enum { MODE_F32 = 0, MODE_F64 = 1 };
+/* MODE_F32_KAHAN and MODE_F32_SUM: the binary32 step of MODE_F32 (same k, phi, increments) with
+ * ln w summed in binary32, with Kahan's compensation or plainly, to measure what the binary64
+ * sum buys (the step's k and phi do not depend on ln w). */
+enum { MODE_F32 = 0, MODE_F64 = 1, MODE_F32_KAHAN = 2, MODE_F32_SUM = 3 };
 
 /* All fields are the user's binary64 values; MODE_F32 rounds each of the
  * derived constants below to binary32 once, MODE_F64 keeps them. */
@@ -315,9 +321,28 @@ static float bf16_round(float x)
     return y;
 }
 
+/* The network's activation: tanh x written as 1 - 2 / (1 + 2^(x c)), c = fl32(2 log2 e), in
+ * binary32 -- the form the sampler evaluates -- with the exponential and the reciprocal
+ * correctly rounded (computed in binary64 and rounded once; the matrix-core path's hardware
+ * exponential and reciprocal are within one ulp of these).  Its absolute error near x = 0 is
+ * that of the reciprocal, about 2^-24, so small activations carry a relative error of order
+ * 2^-24 / |x|; stating the activation in this form makes the oracle round it the way the
+ * sampler does. */
+static float tanh_act_f32(float x)
+{
+    const float c = 2.8853900817779268f;
+    const float y = x * c;
+    const float e = (float)exp2((double)y);
+    const float d = 1.0f + e;
+    const float r = (float)(1.0 / (double)d);
+    return fmaf(-2.0f, r, 1.0f);
+}
+
 /* The learned bias r = out_scale (w3 . h2 + b3), h2 = tanh(W2 h1 + b2), h1 = tanh(W1 x + b1),
- * in binary64 with the kernel's bfloat16 roundings: inputs and both hidden activations are
- * rounded to bfloat16 before they multiply the next layer's weights. */
+ * with the sampler's roundings: inputs and both hidden activations are rounded to bfloat16
+ * before they multiply the next layer's weights; each layer's sum of products (exact for
+ * bfloat16 operands) is formed in binary64 and rounded once to binary32, the activation is
+ * tanh_act_f32, and the output is out_scale times the binary32 sum, in binary32. */
 double oracle_mlp_r(const oracle_params *P, float phi, float N)
 {
     const float *W1 = P->mlp, *b1 = P->mlp + 192, *W2 = P->mlp + 256, *b2 = P->mlp + 4352;
@@ -330,16 +355,16 @@ double oracle_mlp_r(const oracle_params *P, float phi, float N)
     for (int u = 0; u < 64; ++u) {
         double a = (double)b1[u];
         for (int s = 0; s < 3; ++s) a += (double)W1[u * 3 + s] * (double)x[s];
-        h1[u] = (double)bf16_round((float)tanh(a));
+        h1[u] = (double)bf16_round(tanh_act_f32((float)a));
     }
     for (int u = 0; u < 64; ++u) {
         double a = (double)b2[u];
         for (int v = 0; v < 64; ++v) a += (double)W2[u * 64 + v] * h1[v];
-        h2[u] = (double)bf16_round((float)tanh(a));
+        h2[u] = (double)bf16_round(tanh_act_f32((float)a));
     }
     double o = (double)b3;
     for (int u = 0; u < 64; ++u) o += (double)w3[u] * h2[u];
-    return (double)P->out_scale * o;
+    return (double)(P->out_scale * (float)o);
 }
 
 void oracle_mlp_r_batch(const oracle_params *P, const float *phi, const float *N, double *r, int64_t n)
@@ -443,11 +468,12 @@ static double bias_ratio_f64(const oracle_params *P, double phi, double S)
 
 /* One trajectory, binary32 mirror.  Returns the status; writes k, ln w and
  * the final field value. */
-static int simulate_f32(const oracle_params *P, const consts_f32 *c, uint64_t t,
+static int simulate_f32(const oracle_params *P, const consts_f32 *c, uint64_t t, int mode,
                         uint64_t *k_out, double *lw_out, double *phi_out)
 {
     float phi = c->phi_in;
     double lw = 0.0;
+    float lw32 = 0.0f, comp = 0.0f;   /* binary32 sum and Kahan's running compensation */
     uint64_t k = 0;
     float xi4[4];
     float r_mlp = 0.0f;
@@ -473,7 +499,16 @@ static int simulate_f32(const oracle_params *P, const consts_f32 *c, uint64_t t,
         float nphi = phi + dphi;
         float inc = fmaf(r, c->hdN, sxi);
         float dlw = -(r * inc);
-        lw += (double)dlw;
+        if (mode == MODE_F32_KAHAN) {
+            float y = dlw - comp;
+            float tsum = lw32 + y;
+            comp = (tsum - lw32) - y;
+            lw32 = tsum;
+        } else if (mode == MODE_F32_SUM) {
+            lw32 += dlw;
+        } else {
+            lw += (double)dlw;
+        }
         if (nphi > c->phi_uv) nphi = c->two_uv - nphi;
         phi = nphi;
         k += 1;
@@ -482,7 +517,9 @@ static int simulate_f32(const oracle_params *P, const consts_f32 *c, uint64_t t,
         else if (phi > c->phi_esc) status = ST_ESCAPED;
     }
     *k_out = k;
-    *lw_out = lw;
+    if (mode == MODE_F32_KAHAN) *lw_out = (double)lw32 - (double)comp;
+    else if (mode == MODE_F32_SUM) *lw_out = (double)lw32;
+    else *lw_out = lw;
     *phi_out = (double)phi;
     return status;
 }
@@ -543,10 +580,10 @@ int oracle_simulate(const oracle_params *P, uint64_t t0, uint64_t stride, uint64
     for (int64_t i = 0; i < (int64_t)n; ++i) {
         uint64_t t = t0 + (uint64_t)i * stride;
         int st;
-        if (mode == MODE_F32)
-            st = simulate_f32(P, &c, t, &k_out[i], &lw_out[i], &phi_out[i]);
-        else
+        if (mode == MODE_F64)
             st = simulate_f64(P, t, &k_out[i], &lw_out[i], &phi_out[i]);
+        else
+            st = simulate_f32(P, &c, t, mode, &k_out[i], &lw_out[i], &phi_out[i]);
         status_out[i] = st;
     }
     return used;

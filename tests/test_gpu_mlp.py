@@ -39,7 +39,8 @@ def test_mlp_forward_matches_oracle(fpt, seed, scale):
     r_ref = O.mlp_r(model, phi, N)
     err = np.abs(r_gpu - r_ref)
     print(f"seed {seed}: r range [{r_ref.min():.3f}, {r_ref.max():.3f}], max |dr| {err.max():.2e}, "
-          f"99.9% {np.quantile(err, 0.999):.2e}, median {np.median(err):.2e}")
+          f"99.9% {np.quantile(err, 0.999):.2e}, median {np.median(err):.2e}, "
+          f"bit-identical {np.mean(r_gpu.astype(np.float32) == r_ref.astype(np.float32)):.4f}")
     assert np.quantile(err, 0.999) < 5e-3 * params.out_scale
     assert err.max() < 3e-2 * params.out_scale
     assert np.median(err) < 2e-4 * params.out_scale
@@ -54,7 +55,7 @@ def test_mlp_sampler_matches_oracle(fpt, every):
     k = dump.k[:inst.n_traj].astype(np.uint64)
     same = k == tr.k
     print(f"every {every}: identical step counts {same.mean():.4f}")
-    assert same.mean() > 0.95
+    assert same.mean() > 0.99
     # One activation flipping to the neighbouring bfloat16 moves r by ~ |w| 2^-8 ~ 1e-3 (the
     # forward test bounds it); that happens in ~1% of evaluations, each of which changes the
     # log-weight increment by ~ dr sqrt(dN) sigma / sigma ~ 1e-3 * 0.03.  Over the ~2e3
@@ -104,7 +105,7 @@ def test_bump_potential_constant_network_bit_exact(fpt, every):
     tr = O.simulate(to_model(rnd), 0, rnd.n_traj)
     same = dump.k[:rnd.n_traj].astype(np.uint64) == tr.k
     print(f"bump, random network, every {every}: identical step counts {same.mean():.3f}")
-    assert same.mean() > 0.9
+    assert same.mean() > 0.99
     lw_rel = np.abs(dump.lw[same] - tr.lw[same]) / np.maximum(1.0, np.abs(tr.lw[same]))
     assert np.median(lw_rel) < 3e-4
 
