@@ -8,10 +8,10 @@ this package is the thin Python binding over it.
 """
 from ._lib import (BIAS_MLP, BIAS_NOISE_SCALED, BIAS_NONE, BIAS_POWER, POT_FLAT, POT_QUADRATIC,
                    POT_QUADRATIC_BUMP, ST_CENSORED, ST_ENDED, ST_ESCAPED, PyfptError)
-from .api import (Dump, Records, Result, combine, device_cus, layout, mlp_forward, proposal_loss_grad, proposal_records,
+from .api import (COMBINE_NO_EXTRAPOLATION, Dump, Records, Result, combine, device_cus, layout, mlp_forward, proposal_loss_grad, proposal_records,
                   run, run_batch, run_single_abi, train_proposal)
 
-__all__ = ["combine", "run", "run_batch", "run_single_abi", "layout", "device_cus", "mlp_forward", "proposal_records",
+__all__ = ["COMBINE_NO_EXTRAPOLATION", "combine", "run", "run_batch", "run_single_abi", "layout", "device_cus", "mlp_forward", "proposal_records",
            "proposal_loss_grad", "train_proposal", "Result", "Dump", "Records", "PyfptError",
            "POT_QUADRATIC", "POT_QUADRATIC_BUMP", "POT_FLAT", "BIAS_NONE", "BIAS_NOISE_SCALED", "BIAS_POWER",
            "BIAS_MLP", "ST_ENDED", "ST_CENSORED", "ST_ESCAPED"]

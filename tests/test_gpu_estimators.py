@@ -1,28 +1,37 @@
 """The estimators of Sec. 2.4 and Sec. 3 on the GPU against what the paper reports.
 
+Agreement is judged by `helpers.check_z` (at most 1 % of bins beyond 3 sigma, or a binomial tail
+of at least 0.001 for small sets, and a chi^2 p-value of at least 0.001).
+
 * Lognormal estimator and normality gate (Sec. 2.4): in the drift-dominated case the
-  D'Agostino-Pearson p-values of ln w pass the 0.5 % gate and the lognormal estimate agrees
-  with the naive one where both are trusted.
-* Interim case (Sec. 3.2: m = 0.1, phi_in = phi_UV = sqrt 42, A = 1.5, 2e5 runs): the gate
-  passes and the lognormal estimate agrees with the Edgeworth expansion (App. B, cumulants
-  from the backward equation) in the near tail, where the paper finds agreement.
-* Multi-bias reconstruction (Sec. 3.2, 3.3): A = 0, 1, 2, 3 in one batched launch combined bin
-  by bin; every contributing estimate is consistent with the combination, and the combination
-  reaches far below direct sampling.
+  D'Agostino-Pearson p-values of ln w are uniform (Kolmogorov-Smirnov), the number of bins below
+  the 0.5 % gate is what that rate gives, and the lognormal estimate agrees with the naive one
+  where both are trusted.
+* Interim case (Sec. 3.2: m = 0.1, phi_in = phi_UV = sqrt 42): the lognormal estimates with
+  A = 1.5 (2e5 runs) and the multi-bias reconstruction of A = 0, 1, 2, 3 agree with the
+  saddle-point density on the exact cumulant generating function (tests/golden, written from
+  the oracle), down to P ~ 1e-13 and 1e-40.
+* Multi-bias reconstruction (Sec. 3.2, 3.3): every contributing amplitude is consistent with the
+  others (leave-one-out), and the combination reaches far below direct sampling.
 * Power-law bias (Sec. 3.4, m = 0.001): with A_p tuned to put the classical sample mean 8
   standard deviations above the target mean, |r| of log10 w with N grows from p = 1 and peaks
   near p = 3, where the paper finds the optimum.
+* The large-run bump potential at 7e6 runs: the combination agrees with the saddle-point density
+  of the bump potential's own cumulants wherever that series has converged, and reaches below
+  1e-40 with errors under half a decade.
 """
 import dataclasses
 import math
 
 import numpy as np
 import pytest
-from scipy import optimize
+from scipy import optimize, stats
 
 import oracle as O
 from oracle import refmath as R
 import workloads as W
+from conftest import read_golden
+from helpers import check_z, z_two_sided
 
 pytestmark = pytest.mark.gpu
 
@@ -51,15 +60,16 @@ def test_lognormal_gate_and_estimator_drift_case(fpt):
             err = np.sqrt(r.rel_err_jk ** 2 + (0.5 * (r.rel_err_ln_hi + r.rel_err_ln_lo)) ** 2)
             z = (np.exp(r.log_p_ln - r.log_p) - 1) / err
             mz = np.median(np.abs(z[trusted])) if trusted.any() else float("nan")
-        print(f"{inst.name}: populated bins {pop.sum()}, gate failures {np.sum(pv[pop] < 0.005)}, "
+        fails = int(np.sum(pv[pop] < 0.005))
+        print(f"{inst.name}: populated bins {pop.sum()}, gate failures {fails}, "
               f"median p {np.median(pv[pop]):.3f}, trusted {trusted.sum()}, median |z| {mz:.2f}")
         assert pop.sum() >= 20
-        assert np.mean(pv[pop] < 0.005) <= 0.05
-        assert np.median(pv[pop]) > 0.1
-        assert r.lognormal_accepted() or np.sum(pv[pop] < 0.005) <= 2
+        # for normal ln w the p-values are uniform: as many gate failures as a 0.5 % rate gives
+        assert stats.kstest(pv[pop], "uniform").pvalue >= 1e-3
+        assert fails == 0 or stats.binom.sf(fails - 1, int(pop.sum()), 0.005) >= 1e-3
         # the naive estimate is trusted only where n_j > exp(sigma^2_lnw) (none for A >= 2 here)
         if trusted.sum() >= 10:
-            assert np.mean(np.abs(z[trusted]) < 3) >= 0.9
+            check_z(z[trusted], None, inst.name + " naive vs lognormal")
         compared += trusted.sum()
     assert compared >= 20
 
@@ -72,64 +82,70 @@ def _interim(A, n, stream, edges, dN=1e-3):
 
 
 @pytest.fixture(scope="module")
-def interim(fpt):
+def interim():
+    """Bins of width 0.02 over [9.2, 15] and the stored reference on them: log P and its error
+    (tests/golden/tail_reference_interim.txt, written by make_tail_references.py from the
+    oracle's saddle-point density on the exact cumulant generating function)."""
+    rows = np.array([[float(v) for v in r.split()] for r in read_golden("tail_reference_interim.txt")])
     edges = np.round(np.arange(9.2, 15.0 + 1e-9, 0.02), 10)
-    mdl = O.Model(m=0.1, phi_in=math.sqrt(42.0), phi_uv=math.sqrt(42.0))
-    mu, sig, gam, kap = R.edgeworth_for(mdl, n_grid=200001)
-    dN = 1e-3
-
-    def edgeworth_bins(e):
-        out = []
-        for a, b in zip(e[:-1], e[1:]):
-            x = np.linspace(a, b, 65)
-            out.append(np.trapezoid(R.edgeworth_pdf(x - dN, mu, sig, gam, kap), x) / (b - a))
-        return np.array(out)
-    return edges, (mu, sig, gam, kap), edgeworth_bins(edges)
+    assert len(rows) == len(edges) - 1 and np.allclose(rows[:, 1], edges[:-1], atol=1e-9)
+    return edges, rows[:, 3], rows[:, 4]
 
 
-def test_interim_case_lognormal_matches_edgeworth(fpt, interim):
-    edges, (mu, sig, gam, kap), ref = interim
-    print(f"[case] interim A = 1.5: Edgeworth mu {mu:.5f} sigma {sig:.5f} gamma {gam:.4f} kappa {kap:.4f}", flush=True)
+def _ln_errors(r):
+    with np.errstate(divide="ignore"):
+        return -np.log1p(-r.rel_err_ln_lo), np.log1p(r.rel_err_ln_hi)
+
+
+def test_interim_case_lognormal_matches_exact_reference(fpt, interim):
+    """Sec. 3.2's interim case with A = 1.5 and 2e5 runs: the lognormal estimate (Cox interval) in
+    every bin with at least 30 runs agrees with the exact-CGF saddle-point reference, and the
+    estimates reach below 1e-10 (the paper reaches 1e-10 with this bias)."""
+    edges, ref, ref_err = interim
+    print("[case] interim A = 1.5", flush=True)
     r, _, _ = fpt.run(_interim(1.5, 200_000, 0, edges), 0, block=512, wg_per_cu=2, chunk=1)
     B = r.n_bins
-    n = r.count[:B].astype(float)
-    pv = r.normal_p
-    c = 0.5 * (edges[:-1] + edges[1:])
-    use = (n >= 100) & np.isfinite(r.log_p_ln) & (c <= mu + 3.5 * sig)
-    err = 0.5 * (r.rel_err_ln_hi + r.rel_err_ln_lo)
-    z = (np.exp(r.log_p_ln[use]) / ref[use] - 1) / err[use]
-    reach = np.exp(r.log_p_ln[np.isfinite(r.log_p_ln) & (n >= 100)]).min()
-    print(f"bins compared {use.sum()}, median |z| {np.median(np.abs(z)):.2f}, max |z| {np.max(np.abs(z)):.2f}; "
-          f"gate failures {np.sum(pv[n >= 8] < 0.005)} of {np.sum(np.isfinite(pv))}; reach P {reach:.2e}")
-    assert use.sum() >= 20
-    assert np.mean(np.abs(z) < 3) >= 0.9
-    assert np.mean(pv[np.isfinite(pv)] < 0.005) <= 0.05
-    assert reach < 1e-8
+    n = r.count[:B]
+    lo, hi = _ln_errors(r)
+    use = (n >= 30) & np.isfinite(r.log_p_ln)
+    z = z_two_sided(r.log_p_ln - ref, np.sqrt(lo ** 2 + ref_err ** 2), np.sqrt(hi ** 2 + ref_err ** 2))
+    check_z(z[use], None, "interim A=1.5 lognormal vs exact reference")
+    pv = r.normal_p[n >= 8]
+    pv = pv[np.isfinite(pv)]
+    fails = int(np.sum(pv < 0.005))
+    reach = float(np.exp(ref[use]).min())
+    print(f"bins {use.sum()}, reach P {reach:.2e}, gate failures {fails} of {pv.size}")
+    assert use.sum() >= 60 and reach < 1e-10
+    assert fails == 0 or stats.binom.sf(fails - 1, pv.size, 0.005) >= 1e-3
 
 
 def test_multi_bias_reconstruction_interim_case(fpt, interim):
-    edges, (mu, sig, gam, kap), ref = interim
+    """A = 0, 1, 2, 3 with 2.5e5 runs each in one batched launch.  Per-bin estimator (3), with and
+    without the no-extrapolation rule: the combination agrees with the exact reference in every
+    bin it covers, and reaches P < 1e-35 (1e-20 with the rule).  Each amplitude's estimates agree
+    with the combination of the other three (leave-one-out) under the whole-result gate (2)."""
+    edges, ref, ref_err = interim
     insts = [_interim(A, 250_000, i, edges) for i, A in enumerate((0.0, 1.0, 2.0, 3.0))]
     print("[case] interim multi-bias A = 0, 1, 2, 3", flush=True)
     results, _, _ = fpt.run_batch(insts, 0, block=512, wg_per_cu=2, chunk=1)
-    lp, el, nu = fpt.combine(results, 2)
-    ok = nu > 0
-    print(f"combined bins {ok.sum()}, reach P {np.exp(lp[ok]).min():.2e}, direct-sampling reach "
-          f"{np.exp(results[0].log_p[results[0].count[:results[0].n_bins] > 400]).min():.2e}")
-    # every contributing estimate is consistent with the combination
+    reach = {}
+    for est in (3, 3 + fpt.COMBINE_NO_EXTRAPOLATION):
+        lp, el, nu = fpt.combine(results, est)
+        ok = nu > 0
+        z = (lp[ok] - ref[ok]) / np.sqrt(el[ok] ** 2 + ref_err[ok] ** 2)
+        check_z(z, None, f"interim combination (estimator {est}) vs exact reference")
+        reach[est] = float(np.exp(lp[ok]).min())
+        print(f"estimator {est}: combined bins {ok.sum()}, reach P {reach[est]:.2e}")
+    assert reach[3] < 1e-35 and reach[3 + fpt.COMBINE_NO_EXTRAPOLATION] < 1e-20
+    direct = results[0].count[:results[0].n_bins] > 400
+    assert np.exp(results[0].log_p[direct]).min() > 1e-3
     zs = []
-    for r in results:
-        single_lp, single_el, single_nu = fpt.combine([r], 2)
-        both = ok & (single_nu > 0)
-        zs.append((single_lp[both] - lp[both]) / single_el[both])
-    zs = np.concatenate(zs)
-    print(f"consistency: {zs.size} estimates, fraction |z| < 3: {np.mean(np.abs(zs) < 3):.3f}")
-    assert np.mean(np.abs(zs) < 3) >= 0.9
-    assert np.exp(lp[ok]).min() < 1e-20
-    near = ok & (0.5 * (edges[:-1] + edges[1:]) <= mu + 3 * sig)
-    zr = (lp[near] - np.log(ref[near])) / el[near]
-    print(f"near tail vs Edgeworth: {near.sum()} bins, fraction |z| < 3: {np.mean(np.abs(zr) < 3):.3f}")
-    assert np.mean(np.abs(zr) < 3) >= 0.8
+    for i in range(len(results)):
+        s_lp, s_el, s_nu = fpt.combine([results[i]], 2)
+        o_lp, o_el, o_nu = fpt.combine([results[k] for k in range(len(results)) if k != i], 2)
+        both = (s_nu > 0) & (o_nu > 0)
+        zs.append((s_lp[both] - o_lp[both]) / np.sqrt(s_el[both] ** 2 + o_el[both] ** 2))
+    check_z(np.concatenate(zs), None, "interim leave-one-out consistency (estimator 2)")
 
 
 def test_power_law_bias_pearson_scan(fpt):
@@ -156,33 +172,26 @@ def test_power_law_bias_pearson_scan(fpt):
 
 
 def test_bump_potential_multi_bias(fpt):
-    """The large-run configuration (bump potential, dN = 1e-4, 500 bins) at 7e6 runs: the
-    combined lognormal estimates agree with each contributing amplitude, with the Edgeworth
-    expansion of the bump potential's own cumulants near the peak, and reach below 1e-40 with
-    errors under half a decade."""
+    """The large-run configuration (bump potential, dN = 1e-4, 500 bins) at 7e6 runs: the combined
+    estimates (per-bin estimator 3) agree with the saddle-point density of the bump potential's
+    own ten cumulants wherever that series has converged (to P ~ 1e-7 here), and the combination
+    reaches below 1e-40 with errors under half a decade.  With the no-extrapolation rule the
+    amplitudes whose ln w spreads too widely for their runs drop out and the reach shrinks; it is
+    printed."""
     insts = W.c5_multi(n_total=7_000_000)
     print("[case] bump potential multi-bias, 7e6 runs", flush=True)
     results, _, _ = fpt.run_batch(insts, 0, block=512, wg_per_cu=2, chunk=1)
-    lp, el, nu = fpt.combine(results, 1)
-    ok = nu > 0
-    zs = []
-    for r in results:
-        s_lp, s_el, s_nu = fpt.combine([r], 1)
-        both = ok & (s_nu > 0) & (nu > 1)
-        zs.append((s_lp[both] - lp[both]) / np.sqrt(np.maximum(s_el[both] ** 2 - el[both] ** 2, 1e-30)))
-    zs = np.concatenate(zs)
-    good = ok & (el < 0.5 * math.log(10))
-    reach = lp[good].min() / math.log(10)
-    mdl = O.Model.from_instance(insts[0])
-    mu, sig, gam, kap = R.edgeworth_for(mdl, n_grid=200001)
-    e = results[0].edges
-    c = 0.5 * (e[:-1] + e[1:])
-    near = ok & (np.abs(c - mu) <= 2.5 * sig)
-    ref = np.array([np.trapezoid(R.edgeworth_pdf(np.linspace(a, b, 33) - insts[0].dN, mu, sig, gam, kap),
-                                 np.linspace(a, b, 33)) / (b - a) for a, b in zip(e[:-1], e[1:])])
-    zr = (lp[near] - np.log(ref[near])) / el[near]
-    print(f"consistency {zs.size} estimates, |z| < 3: {np.mean(np.abs(zs) < 3):.3f}; reach log10 P {reach:.1f}; "
-          f"near peak vs Edgeworth ({near.sum()} bins, gamma {gam:.3f}): |z| < 3: {np.mean(np.abs(zr) < 3):.3f}")
-    assert np.mean(np.abs(zs) < 3) >= 0.9
-    assert reach < -40
-    assert near.sum() >= 10 and np.mean(np.abs(zr) < 3) >= 0.8
+    ref, trunc = R.saddlepoint_reference(O.Model.from_instance(insts[0]), insts[0].edges, order=10,
+                                         n_grid=200001)
+    rel = np.isfinite(trunc)
+    for est in (3, 3 + fpt.COMBINE_NO_EXTRAPOLATION):
+        lp, el, nu = fpt.combine(results, est)
+        ok = (nu > 0) & rel
+        z = (lp[ok] - ref[ok]) / np.sqrt(el[ok] ** 2 + trunc[ok] ** 2)
+        check_z(z, None, f"bump combination (estimator {est}) vs saddle point")
+        good = (nu > 0) & (el < 0.5 * math.log(10))
+        reach = lp[good].min() / math.log(10)
+        print(f"estimator {est}: {ok.sum()} bins against the reference (to P {np.exp(ref[ok]).min():.1e}); "
+              f"reach log10 P {reach:.1f} with errors under half a decade")
+        if est == 3:
+            assert ok.sum() >= 80 and reach < -40
