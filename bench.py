@@ -23,10 +23,19 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 # VALU issue peak of MI355X: 256 CUs x 4 SIMDs x 32 lanes per clock x 2.4 GHz = 7.86e13
-# lane-ops/s, i.e. the 157.3 TFLOP/s fp32 vector peak divided by 2 flops per FMA.  Measured on
-# the chip: 32-bit add/mul/logic/move issue at 32 lanes per clock per SIMD, fma, 32x32 integer
-# multiplies, f64 add and conversions at 16 (they occupy two issue slots).
+# lane-ops/s, i.e. the 157.3 TFLOP/s fp32 vector peak divided by 2 flops per FMA.  In the step
+# kernel every VALU instruction kind it uses issues at that rate: its counters show 70.4 VALU
+# instructions per wave-step in 171.4 SIMD-cycles, 29.5 of them fma, 32x32 integer multiplies,
+# f64 adds and conversions; at two issue slots for those the wave-step would need 199.8 cycles.
 PEAK_LANE_OPS = 256 * 4 * 32 * 2.4e9
+# MI355X binary32 vector peak (packed FMA on every lane), for the FLOP reading of the roofline
+PEAK_FP32_FLOPS = 157.3e12
+# Binary32 flops per trajectory-step: the algorithmic count of the step's arithmetic (about 35
+# for half a Box-Muller pair with its log, sqrt and sincos, 13 for the step, 2 for the uniforms)
+# and the count of the compiled kernel from its counters (SQ_INSTS_VALU_FLOPS_FP32 per
+# trajectory-step), profiles/fpt_step_kernel_c2_sweep_valu_counters.md
+FLOP_PER_STEP_ALGORITHMIC = 50.0
+FLOP_PER_STEP_COUNTED = 61.7
 # Algorithmic lane operations per trajectory-step of the quadratic, noise-scaled path: the VALU
 # instructions of the compiled four-step pass of fpt_step_kernel<0,1,false>, loop control and
 # retirement excluded (fma, three-input xor and 32x32->64 multiply one each):
@@ -100,6 +109,9 @@ def parse():
                    help="time the learned-bias sampler alone (untrained network, r ~ 1) on the diffusion case")
     p.add_argument("--c3", action="store_true",
                    help="the 64-instance batched sweep in one graph-replayed launch with the autotuned shape")
+    p.add_argument("--no-c3", action="store_true",
+                   help="skip the batched sweep in the main line (it adds about 40 s)")
+    p.add_argument("--c3-steps", type=int, default=2, help="timed passes of the batched sweep in the main line")
     p.add_argument("--copy-calibration", action="store_true",
                    help="only copy 1 GiB device-to-device 3 times (scale reference for HBM byte counters)")
     return p.parse_args()
@@ -118,8 +130,20 @@ def copy_calibration():
     print(json.dumps({"copy_bytes_read": src.numel() * 4, "copy_bytes_written": dst.numel() * 4, "launches": 3}))
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(insts, target_s):
-    """The oracle (binary32 mirror, all host threads) on a bounded sample of the same runs."""
+    """The oracle (binary32 mirror, all host threads) on a bounded sample of the same runs, and
+    on one thread over the first runs of the same sample (a few seconds)."""
     import numpy as np
     import oracle as O
     to_model = O.Model.from_instance
@@ -143,7 +167,20 @@ def cpu_baseline(insts, target_s):
         steps += int(tr.k.sum())
         threads = tr.threads
         sample.append(f"{inst.name}:{n}")
+    # one thread: the first ids of the first drift-dominated instance (about 3 s)
+    one = insts[0]
+    n1, s1, e1 = 64, 0, 0.0
+    while True:
+        t0 = time.perf_counter()
+        tr = O.simulate(to_model(one), 0, n1, threads=1)
+        e1 = time.perf_counter() - t0
+        s1 = int(tr.k.sum())
+        if e1 >= 1.5 or n1 >= one.n_traj:
+            break
+        n1 = int(min(one.n_traj, n1 * min(8.0, max(2.0, 3.0 / max(e1, 1e-3)))))
     return {"value": steps / elapsed, "unit": "traj-steps/s", "cores": threads, "kind": "oracle",
+            "cpu_model": cpu_model(), "single_core": s1 / e1,
+            "single_core_sample": f"{one.name}: first {n1} ids, {s1} steps in {e1:.2f} s on one thread",
             "sample": "first ids of each instance: " + ", ".join(sample) + f"; {steps} steps in {elapsed:.1f} s"}
 
 
@@ -411,43 +448,49 @@ def mlp_sampler_run(args):
     print(json.dumps(out), flush=True)
 
 
-def c3_run(args):
+def c3_run(args, steps=None, warmup=None, quiet=False):
     """The batched sweep (64 instances of uneven length, 1e6 runs each) as one persistent launch,
-    replayed from a HIP graph, launch shape and queue chunk from the library's autotuner."""
+    replayed from a HIP graph, launch shape and queue chunk from the library's autotuner.
+    Returns the result line (printed unless quiet)."""
     import torch
     import paper_2206_11234_amd as F
     import workloads as W
 
     torch.cuda.set_device(0)
+    steps = args.steps if steps is None else steps
+    warmup = args.warmup if warmup is None else warmup
     insts = W.c3(args.n_traj)
     side = torch.cuda.Stream()   # graph capture needs a non-null stream
     kw = dict(block=0, wg_per_cu=0, chunk=0)
     with torch.cuda.stream(side):
         # the first call runs the autotuner; one timed pass gives the kernel time (HIP events)
         _, _, tm = F.run_batch(insts, 0, timing=True, **kw)
-        for _ in range(args.warmup):
+        for _ in range(warmup):
             F.run_batch(insts, 0, use_graph=True, **kw)
         side.synchronize()
         steps_total = 0
         t_all = time.perf_counter()
-        for s in range(args.steps):
+        for s in range(steps):
             t0 = time.perf_counter()
             results, _, _ = F.run_batch(insts, 0, use_graph=True, **kw)
             side.synchronize()
             steps_total += sum(r.total_steps for r in results)
             print(f"[c3] pass {s} {(time.perf_counter() - t0) * 1e3:.1f} ms", file=sys.stderr, flush=True)
         wall = time.perf_counter() - t_all
-    steps_per_pass = steps_total / args.steps
+    steps_per_pass = steps_total / steps
     lens = [r.total_steps / i.n_traj for r, i in zip(results, insts)]
     out = {"metric": "weighted traj-steps/s", "value": steps_total / wall, "unit": "traj-steps/s",
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": wall / args.steps * 1e3,
+           "steps": steps, "warmup": warmup, "ms_per_step": wall / steps * 1e3,
            "kernel_ms": tm[0], "kernel_rate": steps_per_pass / (tm[0] / 1e3),
+           "issue_frac": OPS_PER_STEP * steps_per_pass / (tm[0] / 1e3) / PEAK_LANE_OPS,
            "config": {"workload": "C3 batched sweep: 64 instances from splitmix64(0), phi_in~U[3,12], "
                                   "m in {0.01,0.1,0.5,1}, A in {0..6}, wall on/off, dN in {1e-3,5e-4}, "
                                   "1e6 runs each, one graph-replayed launch, autotuned shape",
                       "instances": len(insts), "runs_per_instance": args.n_traj, "steps_per_pass": steps_per_pass,
                       "mean_len_min": min(lens), "mean_len_max": max(lens)}}
-    print(json.dumps(out), flush=True)
+    if not quiet:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def main():
@@ -512,6 +555,7 @@ def main():
     value = steps_total / wall
     kmean = sum(kern_ms) / len(kern_ms) / 1e3
     achieved = OPS_PER_STEP * steps_per_pass / kmean
+    kernel_steps_per_s = steps_per_pass / kmean
     out = {
         "metric": "weighted traj-steps/s",
         "value": value,
@@ -535,8 +579,17 @@ def main():
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": PEAK_LANE_OPS / 1e12,
                      "unit": "Tlane-op/s", "frac": achieved / PEAK_LANE_OPS, "traffic": TRAFFIC, "traffic_unit": "bytes/launch",
                      "kernel": "fpt_step_kernel", "kernel_ms": kmean * 1e3,
-                     "ops_per_step": OPS_PER_STEP},
+                     "ops_per_step": OPS_PER_STEP,
+                     "frac_reading": "VALU issue: compiled lane-ops per step over the lane-op issue peak",
+                     "frac_flop": FLOP_PER_STEP_ALGORITHMIC * kernel_steps_per_s / PEAK_FP32_FLOPS,
+                     "frac_flop_counted": FLOP_PER_STEP_COUNTED * kernel_steps_per_s / PEAK_FP32_FLOPS,
+                     "flop_per_step": FLOP_PER_STEP_ALGORITHMIC, "flop_per_step_counted": FLOP_PER_STEP_COUNTED,
+                     "flop_peak": PEAK_FP32_FLOPS / 1e12},
     }
+    if not args.no_c3:
+        c3 = c3_run(args, steps=args.c3_steps, warmup=1, quiet=True)
+        out["c3_batched"] = {k: c3[k] for k in ("value", "unit", "steps", "ms_per_step", "kernel_ms", "kernel_rate",
+                                                "issue_frac", "config")}
     if not args.no_learned:
         out["learned_vs_fixed"] = learned_summary(learned_gain(args))
     if not args.no_cpu:
