@@ -178,6 +178,11 @@ typedef struct pyfpt_instance {
  *   pearson_r          Pearson's correlation coefficient of ln w (equivalently log10 w) with N over
  *                      the runs that ended (Sec. 3.4: |r| near 1 means a squeezed (N, w) scatter, the
  *                      criterion for tuning the power p of the bias A_p phi^p); NaN if undefined
+ *   ess[B]             Kish's effective sample size of the bin, (sum w)^2 / sum w^2 = exp(2 lse_w - lse_w2)
+ *                      (0 for an empty bin)
+ *   lognormal_gate     1 when every bin with n_j >= 8 (a defined normality p-value) has p >= 0.005, the
+ *                      paper's condition for using the lognormal estimator on the result (Sec. 2.4),
+ *                      else 0
  */
 typedef struct pyfpt_result {
     uint64_t *counts;
@@ -193,6 +198,7 @@ typedef struct pyfpt_layout {
     uint64_t log_p_ln, rel_err_ln_lo, rel_err_ln_hi, normal_p;
     uint64_t lse_w_all, lse_w2_all, lse_wk, lse_wk2, sum_k2;
     uint64_t pearson_r;
+    uint64_t ess, lognormal_gate;
 } pyfpt_layout;
 
 /* Per-trajectory record of runs t with t % stride == 0 and t / stride < n

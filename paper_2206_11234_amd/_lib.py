@@ -57,7 +57,7 @@ class pyfpt_layout(ctypes.Structure):
         "n_counts", "n_values", "count", "jk_count", "n_traj", "total_steps",
         "lse_w", "lse_w2", "jk_lse_w", "mean_lnw", "m2_lnw", "m3_lnw", "m4_lnw",
         "log_p", "rel_err_jk", "rel_err_kish", "log_p_ln", "rel_err_ln_lo", "rel_err_ln_hi", "normal_p",
-        "lse_w_all", "lse_w2_all", "lse_wk", "lse_wk2", "sum_k2", "pearson_r")]
+        "lse_w_all", "lse_w2_all", "lse_wk", "lse_wk2", "sum_k2", "pearson_r", "ess", "lognormal_gate")]
 
 
 class pyfpt_dump(ctypes.Structure):

@@ -124,12 +124,10 @@ class Result:
     def normal_p(self):
         return self._v(self.lay.normal_p, self.n_bins)
 
-    def lognormal_accepted(self, threshold: float = 0.005, min_count: int = 8) -> bool:
-        """The paper's gate (Sec. 2.4): the lognormal estimator is used when no bin with a
-        defined normality p-value falls below the threshold (0.5 %)."""
-        p = self.normal_p[self.count[:self.n_bins] >= min_count]
-        p = p[np.isfinite(p)]
-        return bool(np.all(p >= threshold))
+    def lognormal_accepted(self) -> bool:
+        """The paper's gate (Sec. 2.4), as the library evaluates it: no bin with a normality
+        p-value (n_j >= 8) below 0.5 %."""
+        return bool(self.values[self.lay.lognormal_gate] == 1.0)
 
     @property
     def lse_w_all(self):
@@ -156,8 +154,8 @@ class Result:
         return float(self.values[self.lay.pearson_r])
 
     def ess(self):
-        with np.errstate(invalid="ignore"):
-            return np.exp(2 * self.lse_w[:self.n_bins] - self.lse_w2[:self.n_bins])
+        """Kish's effective sample size per bin, as the library computes it."""
+        return self._v(self.lay.ess, self.n_bins)
 
 
 @dataclass

@@ -95,6 +95,7 @@ struct ResultLayout {
     uint64_t log_p_ln, rel_err_ln_lo, rel_err_ln_hi, normal_p;
     uint64_t lse_w_all, lse_w2_all, lse_wk, lse_wk2, sum_k2;
     uint64_t pearson_r;
+    uint64_t ess, lognormal_gate;
 };
 
 __host__ __device__ inline ResultLayout result_layout(uint32_t n_bins, uint32_t n_sub) {
@@ -127,6 +128,8 @@ __host__ __device__ inline ResultLayout result_layout(uint32_t n_bins, uint32_t 
     L.lse_wk2 = v++;
     L.sum_k2 = v++;
     L.pearson_r = v++;
+    L.ess = v; v += B;
+    L.lognormal_gate = v++;
     L.n_values = v;
     return L;
 }

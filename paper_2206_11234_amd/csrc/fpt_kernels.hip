@@ -514,6 +514,7 @@ __global__ __launch_bounds__(256) void fpt_merge_kernel(MergeArgs a) {
         }
         a.counts[m.counts_off + RL.n_traj] = m.n_traj;
         a.counts[m.counts_off + RL.total_steps] = static_cast<uint64_t>(steps);
+        V[RL.lognormal_gate] = 1.0;     // cleared by the finalize kernel where a bin fails
     }
 }
 
@@ -608,7 +609,13 @@ __global__ __launch_bounds__(256) void fpt_finalize_kernel(MergeArgs a) {
         const double k2 = exp(V[RL.lse_w2 + lr] - 2.0 * l) - 1.0 / nt;
         V[RL.rel_err_kish + lr] = (cnt == 0) ? NAN : sqrt(fmax(k2, 0.0));
         if (cnt == 0) V[RL.rel_err_jk + lr] = NAN;
+        // Kish's effective sample size of the bin, (sum w)^2 / sum w^2
+        V[RL.ess + lr] = (cnt == 0) ? 0.0 : exp(2.0 * l - V[RL.lse_w2 + lr]);
         lognormal_bin(V, RL, lr, cnt, log(width) + log(nt));
+        // the paper's gate (Sec. 2.4): the lognormal estimator holds for the result when no bin
+        // with a normality p-value (n_j >= 8) falls below 0.5 %; every failing bin writes 0
+        const double pv = V[RL.normal_p + lr];
+        if (cnt >= 8 && pv == pv && pv < 0.005) V[RL.lognormal_gate] = 0.0;
     }
 }
 

@@ -964,6 +964,8 @@ int pyfpt_result_layout(int32_t n_bins, int32_t n_sub, pyfpt_layout *out) {
     out->lse_wk2 = L.lse_wk2;
     out->sum_k2 = L.sum_k2;
     out->pearson_r = L.pearson_r;
+    out->ess = L.ess;
+    out->lognormal_gate = L.lognormal_gate;
     return PYFPT_OK;
 }
 
@@ -1081,14 +1083,7 @@ static int pyfpt_combine_impl(const pyfpt_result *res, int32_t n_res, int32_t n_
             V = vbuf.data();
         }
         int est = kind;
-        if (est == 2) {
-            bool gate = true;
-            for (uint32_t j = 0; j < B; ++j) {
-                const double p = V[L.normal_p + j];
-                if (std::isfinite(p) && p < 0.005) gate = false;
-            }
-            est = gate ? 1 : 0;
-        }
+        if (est == 2) est = V[L.lognormal_gate] == 1.0 ? 1 : 0;
         for (uint32_t j = 0; j < B; ++j) {
             const double n = static_cast<double>(C[L.count + j]);
             // naive estimate, trusted when n > 400 and n > exp(var ln w); lognormal estimate,

@@ -78,12 +78,22 @@ def assert_histogram_matches(res, h, rel=1e-12):
     for got, want in ((res.rel_err_ln_hi[f4], hi[f4]), (res.rel_err_ln_lo[f4], lo[f4])):
         with np.errstate(invalid="ignore"):
             assert np.all((got == want) | (np.abs(got - want) <= 1e-7 * want + 1e-12))
+    # Kish ESS per bin and the whole-result normality gate, as the library reports them
+    ess_ref = h.ess()
+    f6 = h.count[:B] > 0
+    assert np.all(res.ess()[~f6] == 0.0)
+    assert np.all(np.abs(res.ess()[f6] - ess_ref[f6]) <= 1e-9 * ess_ref[f6])
     pv = h.normal_p[:B]
     f5 = np.isfinite(pv)
     assert np.array_equal(np.isfinite(res.normal_p), f5), (np.nonzero(np.isfinite(res.normal_p) != f5)[0][:5])
     # the p-value depends on the third and fourth moments (agreeing to ~1e-7 relative)
     bad = np.nonzero(~(np.abs(res.normal_p[f5] - pv[f5]) <= 1e-4 * pv[f5] + 1e-9))[0]
     assert bad.size == 0, ("normal_p", res.normal_p[f5][bad][:5], pv[f5][bad][:5])
+    # the gate as the paper states it, from the oracle's p-values (decided identically unless a
+    # p-value lies within the comparison's tolerance of 0.005)
+    near = np.abs(pv[f5] - 0.005) <= 1e-4 * 0.005 + 1e-9
+    if not np.any(near):
+        assert res.lognormal_accepted() == (not np.any(pv[f5] < 0.005))
 
 
 def assert_dump_matches(dump, tr):

@@ -40,7 +40,8 @@ def test_result_layout(lib):
     assert lay.lse_w == 0 and lay.lse_w2 == R and lay.jk_lse_w == 2 * R
     assert lay.log_p == 2 * R + J * R + 4 * R
     assert lay.log_p_ln == lay.log_p + 3 * B and lay.normal_p == lay.log_p + 6 * B
-    assert lay.n_values == 2 * R + J * R + 4 * R + 7 * B + 6
+    assert lay.ess == lay.pearson_r + 1 and lay.lognormal_gate == lay.ess + B
+    assert lay.n_values == 2 * R + J * R + 4 * R + 8 * B + 7
     assert lib.load().pyfpt_result_layout(0, 16, ctypes.byref(lay)) == lib.PYFPT_EINVAL
     assert lib.load().pyfpt_result_layout(10, 1, ctypes.byref(lay)) == lib.PYFPT_EINVAL
 

@@ -193,6 +193,8 @@ def _pack(lib, h, n_sub):
     v[lay.log_p_ln:lay.log_p_ln + B] = lp
     v[lay.rel_err_ln_hi:lay.rel_err_ln_hi + B] = hi
     v[lay.normal_p:lay.normal_p + B] = h.normal_p[:B]
+    pv = h.normal_p[:B]
+    v[lay.lognormal_gate] = 0.0 if np.any(np.isfinite(pv) & (pv < 0.005)) else 1.0
     return c, v
 
 
