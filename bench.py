@@ -81,6 +81,10 @@ def parse():
     p.add_argument("--eval-every", type=int, default=16,
                    help="steps the learned bias is held for (1, 4, 8 or 16); training records use the same groups")
     p.add_argument("--objective", type=int, default=1, help="0: log M2, 1: cross entropy")
+    p.add_argument("--objective-compare", type=int, default=1,
+                   help="also train with objective 0 (log M2) on the same seeds and budget and report it")
+    p.add_argument("--fixed-budget-s", type=float, default=30.0,
+                   help="GPU-seconds the best fixed bias runs for in the measured equal-error comparison (0: skip)")
     p.add_argument("--temper", type=float, default=0.5, help="w_0^temper in the path weights")
     p.add_argument("--train-seed", type=int, default=1)
     p.add_argument("--final-rounds", type=int, default=6, help="rounds of the final stage of the far-tail training (the C5 proposal uses --rounds)")
@@ -331,11 +335,14 @@ def learned_gain(args):
     out = {"workload": f"far-tail window ({lo:g}, {hi:g}] of the diffusion case, P ~ 1e-30", "fixed": [],
            "n_eval": args.n_eval}
 
+    results = {}
+
     def evaluate(inst, label, **kw):
         F.run(dataclasses.replace(inst, n_traj=min(inst.n_traj, 20000)), EVAL_SEED, **kw)   # warm-up
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         res, _, tm = F.run(inst, EVAL_SEED, timing=True, **kw)
+        results[label] = (res, tm[0])
         wall = time.perf_counter() - t0
         st = window_stats(res, lo, hi)
         st.update(label=label, kernel_ms=tm[0], wall_s=wall, steps=res.total_steps,
@@ -377,6 +384,27 @@ def learned_gain(args):
     p1 = W.MlpParams(theta, in_mean=p0.in_mean, in_inv_scale=p0.in_inv_scale, out_scale=1.0,
                      eval_every=args.eval_every)
     learned = evaluate(dataclasses.replace(inst0, mlp=p1), "learned", block=256, wg_per_cu=args.mlp_wg, chunk=1)
+    # the same curriculum, seeds and budget with the second-moment objective (0: log M2, the
+    # weight-variance criterion), whose path weights depend on theta, so every record is kept
+    obj0 = None
+    if args.objective_compare and args.objective != 0:
+        t0 = time.perf_counter()
+        theta0 = p0.values_f32()
+        rep0 = []
+        for si, centre in enumerate(stages):
+            theta0, _, r_stage = F.train_proposal(dataclasses.replace(inst0, target_N=centre), args.train_seed + 100 * si,
+                                                  theta0, window=(centre - 6.0, centre + 6.0), n_sample=args.n_sample,
+                                                  rounds=(args.final_rounds or args.rounds) if si == len(stages) - 1
+                                                  else args.rounds, steps=args.train_steps, max_paths=args.max_paths,
+                                                  lr=args.lr, objective=0, temper=args.temper, stride=1,
+                                                  select=args.select_pilot if si == len(stages) - 1 else 0)
+            rep0 += r_stage
+        train0_s = time.perf_counter() - t0
+        p_obj0 = W.MlpParams(theta0, in_mean=p0.in_mean, in_inv_scale=p0.in_inv_scale, out_scale=1.0,
+                             eval_every=args.eval_every)
+        obj0 = evaluate(dataclasses.replace(inst0, mlp=p_obj0), "learned objective 0", block=256,
+                        wg_per_cu=args.mlp_wg, chunk=1)
+        obj0["train_s"] = train0_s
     # a fixed bias is a candidate only where its window estimate is trusted by the paper's
     # n_j > 400 criterion (Sec. 2.1); with fewer runs its error estimate is itself unreliable
     cands = [f for f in out["fixed"] if f["gpu_s_to_1pct"] and f["count"] > 400]
@@ -391,11 +419,74 @@ def learned_gain(args):
         st["dN"] = dn
         out["learned_dn"].append(st)
     lj = learned["gpu_s_to_1pct_jk"]
+    # measured, not extrapolated: the best fixed bias runs on (id-range shards of n_eval runs)
+    # for args.fixed_budget_s GPU-seconds; the error it reaches is the target eps, and each
+    # learned proposal runs in shards of 2^17 runs (one per lane of the launch) until it reaches
+    # the same eps
+    measured = None
+    if best is not None and args.fixed_budget_s > 0:
+        A_best = float(best["label"].split("=")[1])
+        fx = run_until(F, dataclasses.replace(base, A=A_best), lo, hi, 0.0, args.n_eval, args.fixed_budget_s,
+                       first=results[best["label"]], block=512, wg_per_cu=2, chunk=1)
+        eps_m = fx["median_rel_err_jk"]
+        measured = {"eps": eps_m, "fixed": dict(fx, label=best["label"])}
+        for label, params in (("learned", p1),) + ((("learned objective 0", p_obj0),) if obj0 else ()):
+            lm = run_until(F, dataclasses.replace(inst0, mlp=params), lo, hi, eps_m, 1 << 17, 60.0,
+                           block=256, wg_per_cu=args.mlp_wg, chunk=1)
+            lm["gain"] = fx["gpu_s"] / lm["gpu_s"] if lm["reached"] else None
+            measured[label] = lm
+            print(f"[learned] measured to eps {eps_m:.3f}: {label} {json.dumps(lm)}", file=sys.stderr, flush=True)
+        print(f"[learned] measured fixed: {json.dumps(measured['fixed'])}", file=sys.stderr, flush=True)
     out.update(learned=learned, train_s=train_s, train_rounds=rep, best_fixed=best["label"] if best else None,
+               objective_0=obj0, measured=measured,
                gain=(best["gpu_s_to_1pct"] / lg) if (best and lg) else None,
                gain_with_training=(best["gpu_s_to_1pct"] / (lg + train_s)) if (best and lg) else None,
                gain_jk=(best["gpu_s_to_1pct_jk"] / lj) if (best and lj and best["gpu_s_to_1pct_jk"]) else None)
     return out
+
+
+def run_until(F, inst, lo, hi, eps, shard, budget_s, first=None, **kw):
+    """Runs `inst` in id-range shards of `shard` runs (t_first = 0, shard, 2 shard, ...) until the
+    median jackknife relative error over the window bins (lo, hi] of the merged shards is at most
+    eps, or the kernel time reaches budget_s.  The shards' tables merge exactly (counts and
+    jackknife counts add, log-sums combine by logaddexp; a run's subset is its id mod 16).
+    `first`: an already computed result of the first shard (with its kernel ms).  Returns the
+    kernel GPU-seconds, runs, and the error reached (jackknife and Kish)."""
+    import dataclasses
+    import numpy as np
+    gpu_s, runs, i = 0.0, 0, 0
+    acc = None
+    while True:
+        if first is not None and i == 0:
+            res, ms = first
+        else:
+            res, _, tm = F.run(dataclasses.replace(inst, n_traj=shard, t_first=i * shard), EVAL_SEED, timing=True, **kw)
+            ms = tm[0]
+        gpu_s += ms / 1e3
+        runs += shard
+        i += 1
+        e = res.edges
+        j = np.array([b for b in range(len(e) - 1) if e[b] >= lo - 1e-9 and e[b + 1] <= hi + 1e-9])
+        part = (res.jk_lse_w[:, j], res.jk_count[:, j].astype(np.float64), res.lse_w2[j])
+        if acc is None:
+            acc = [part[0].copy(), part[1].copy(), part[2].copy()]
+        else:
+            acc[0] = np.logaddexp(acc[0], part[0])
+            acc[1] += part[1]
+            acc[2] = np.logaddexp(acc[2], part[2])
+        jk, jc, l2 = acc
+        J = jk.shape[0]
+        l = np.logaddexp.reduce(jk, axis=0)
+        n_sub = np.array([runs // J + (1 if s < runs % J else 0) for s in range(J)], np.float64)
+        with np.errstate(invalid="ignore", divide="ignore", over="ignore"):
+            ratio = np.exp(jk - l[None, :]) * (runs / n_sub[:, None])
+            err_jk = np.std(ratio, axis=0, ddof=1) / np.sqrt(J)
+            err_kish = np.sqrt(np.maximum(np.exp(l2 - 2 * l) - 1.0 / runs, 0.0))
+        err_jk = np.where(jc.sum(axis=0) > 0, err_jk, np.inf)
+        med_jk, med_kish = float(np.median(err_jk)), float(np.median(np.where(np.isfinite(err_jk), err_kish, np.inf)))
+        if med_jk <= eps or gpu_s >= budget_s:
+            return {"gpu_s": gpu_s, "runs": runs, "median_rel_err_jk": med_jk, "median_rel_err_kish": med_kish,
+                    "reached": bool(med_jk <= eps)}
 
 
 def learned_summary(full):
@@ -410,7 +501,12 @@ def learned_summary(full):
             "gain_jackknife": full.get("gain_jk"),
             "note": "GPU-s to 1% median relative error over the window = kernel time x (error / 0.01)^2, "
                     "errors from the Kish ESS (gain_jackknife: the same with jackknife errors); "
-                    "best fixed = lowest among the fixed amplitudes with > 400 window runs"}
+                    "best fixed = lowest among the fixed amplitudes with > 400 window runs",
+            "objective": "cross entropy (1), tempered",
+            "objective_0": ({k: full["objective_0"][k] for k in ("ess", "median_rel_err", "median_rel_err_jk", "log10_p",
+                                                                 "gpu_s_to_1pct", "train_s")}
+                            if full.get("objective_0") else None),
+            "measured": full.get("measured")}
 
 
 def mlp_sampler_run(args):
