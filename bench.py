@@ -246,6 +246,17 @@ def c5_run(args):
     e = results[0].edges
     good = ok & (el < 0.5 * math.log(10.0))          # bins known to better than half a decade
     deepest = int(np.nonzero(good)[0].max()) if good.any() else -1
+    # the same with the no-extrapolation rule: lognormal bins need n_j >= exp(s^2 / 2)
+    lp_s, el_s, nu_s = F.combine(results, 3 + F.COMBINE_NO_EXTRAPOLATION)
+    good_s = (nu_s > 0) & (el_s < 0.5 * math.log(10.0))
+    deep_s = int(np.nonzero(good_s)[0].max()) if good_s.any() else -1
+    strict = {"combined_bins": int((nu_s > 0).sum()), "bins_within_half_decade": int(good_s.sum()),
+              "reach_log10_p": float(lp_s[deep_s] / math.log(10)) if deep_s >= 0 else None,
+              "reach_err_log10": float(el_s[deep_s] / math.log(10)) if deep_s >= 0 else None,
+              "reach_N": float(0.5 * (e[deep_s] + e[deep_s + 1])) if deep_s >= 0 else None,
+              "p_1e-40_N": (float(0.5 * (e[np.argmax((nu_s > 0) & (lp_s < -40 * math.log(10)))]
+                                        + e[np.argmax((nu_s > 0) & (lp_s < -40 * math.log(10))) + 1]))
+                            if np.any((nu_s > 0) & (lp_s < -40 * math.log(10))) else None)}
     out = {"workload": "C5 bump potential, multi-bias A = 0..6" + (" + learned proposal" if learned else "") +
                        ", dN = 1e-4, 500 bins",
            "runs": sum(r.n_traj for r in results), "steps": steps, "wall_s": wall, "kernel_ms": kern_ms, "launches": len(groups),
@@ -254,7 +265,8 @@ def c5_run(args):
            "combined_bins": int(ok.sum()), "bins_within_half_decade": int(good.sum()),
            "reach_log10_p": float(lp[deepest] / math.log(10)) if deepest >= 0 else None,
            "reach_err_log10": float(el[deepest] / math.log(10)) if deepest >= 0 else None,
-           "reach_N": float(0.5 * (e[deepest] + e[deepest + 1])) if deepest >= 0 else None}
+           "reach_N": float(0.5 * (e[deepest] + e[deepest + 1])) if deepest >= 0 else None,
+           "no_extrapolation": strict}
     if learned is not None:
         out["learned"] = learned
     print(json.dumps(out), flush=True)
