@@ -97,6 +97,7 @@ def lib():
                                       ctypes.c_int]
         L.oracle_simulate.restype = ctypes.c_int
         L.oracle_mlp_r_batch.argtypes = [ctypes.POINTER(_Params), f32p, f32p, f64p, ctypes.c_int64]
+        L.oracle_tanh_act.argtypes = [f32p, f32p, ctypes.c_int64]
         vp = ctypes.c_void_p
         L.oracle_records.argtypes = [ctypes.POINTER(_Params), u64p, ctypes.c_int64, ctypes.c_int, ctypes.c_int, u64p,
                                      vp, u64p, f64p, i32p]
@@ -202,6 +203,15 @@ def mlp_r(model: Model, phi, N) -> np.ndarray:
     lib().oracle_mlp_r_batch(ctypes.byref(P), _ptr(phi, ctypes.c_float), _ptr(N, ctypes.c_float),
                              _ptr(out, ctypes.c_double), phi.size)
     return out
+
+
+def tanh_act(x) -> np.ndarray:
+    """The sampler's activation (binary32 in, binary32 out): tanh as a clamped polynomial,
+    accurate to a third of a bfloat16 ulp (see the C source)."""
+    x = np.ascontiguousarray(x, np.float32)
+    y = np.zeros(x.size, np.float32)
+    lib().oracle_tanh_act(_ptr(x, ctypes.c_float), _ptr(y, ctypes.c_float), x.size)
+    return y.reshape(x.shape)
 
 
 # --------------------------------------------------------------------------

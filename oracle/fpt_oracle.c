@@ -321,21 +321,25 @@ static float bf16_round(float x)
     return y;
 }
 
-/* The network's activation: tanh x written as 1 - 2 / (1 + 2^(x c)), c = fl32(2 log2 e), in
- * binary32 -- the form the sampler evaluates -- with the exponential and the reciprocal
- * correctly rounded (computed in binary64 and rounded once; the matrix-core path's hardware
- * exponential and reciprocal are within one ulp of these).  Its absolute error near x = 0 is
- * that of the reciprocal, about 2^-24, so small activations carry a relative error of order
- * 2^-24 / |x|; stating the activation in this form makes the oracle round it the way the
- * sampler does. */
+/* The network's activation in the sampler: tanh to within a third of a bfloat16 ulp (the
+ * precision its result is rounded to), as a clamped polynomial in binary32: x is clamped to
+ * [-3.4, 3.4], beyond which tanh rounds to +-1 in bfloat16, and tanh x ~ x q(|x|), with q of
+ * degree 5 fitted to minimise the largest error in bfloat16 ulps of tanh over [0, 3.4] and the
+ * clamped tail.  q is evaluated by Horner's rule with correctly rounded fused multiply-adds
+ * (fmaf) and the last product is a binary32 multiplication: the sequence the sampler executes,
+ * so that given the same pre-activation the two agree bit for bit.  The pins bound its
+ * distance to tanh; the training tools below use tanh itself. */
 static float tanh_act_f32(float x)
 {
-    const float c = 2.8853900817779268f;
-    const float y = x * c;
-    const float e = (float)exp2((double)y);
-    const float d = 1.0f + e;
-    const float r = (float)(1.0 / (double)d);
-    return fmaf(-2.0f, r, 1.0f);
+    const float xc = fminf(fmaxf(x, -3.4f), 3.4f);
+    const float t = fabsf(xc);
+    float q = 0.005465357564389706f;
+    q = fmaf(q, t, -0.06311261653900146f);
+    q = fmaf(q, t, 0.27104586362838745f);
+    q = fmaf(q, t, -0.47482094168663025f);
+    q = fmaf(q, t, 0.02362865023314953f);
+    q = fmaf(q, t, 0.9999812841415405f);
+    return q * xc;
 }
 
 /* The learned bias r = out_scale (w3 . h2 + b3), h2 = tanh(W2 h1 + b2), h1 = tanh(W1 x + b1),
@@ -370,6 +374,12 @@ double oracle_mlp_r(const oracle_params *P, float phi, float N)
 void oracle_mlp_r_batch(const oracle_params *P, const float *phi, const float *N, double *r, int64_t n)
 {
     for (int64_t i = 0; i < n; ++i) r[i] = oracle_mlp_r(P, phi[i], N[i]);
+}
+
+/* The activation alone, for its pins. */
+void oracle_tanh_act(const float *x, float *y, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i) y[i] = tanh_act_f32(x[i]);
 }
 
 /* Derived constants (Planck units):

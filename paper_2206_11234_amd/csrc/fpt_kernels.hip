@@ -25,6 +25,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "fpt_kernels.h"
 
 namespace fpt {
@@ -271,16 +273,42 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
             // start at k = 0 and refill only between passes, so every lane of the wave is at a
             // multiple of the pass length here and the evaluation points of all lanes coincide.
             const int E = a.mlp_every;
-            const int n_q = E > 4 ? E >> 2 : 1;
-            float r_mlp = 0.0f;
-            for (int q = 0; q < n_q; ++q) {
-                if (q * 4 % E == 0) r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
+            // One evaluation per pass of E = 4, 8 or 16 steps.  The pass's normals do not depend
+            // on the network, so they are drawn before it and the scheduler interleaves their
+            // vector work with the evaluation's matrix-core chains (they are the normals of
+            // counters k/4 .. k/4 + E/4 - 1, the ones the steps would draw; a lane whose run ends
+            // early leaves the rest unused).  The evaluation runs at a raised wave priority, so
+            // that it finishes sooner while the SIMD's other wave fills the gaps with steps.
+            auto pass = [&](auto nq_tag) {
+                constexpr int NQ = decltype(nq_tag)::value;
+                F4 zz[NQ];
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) zz[q] = normals4((k >> 2) + q, t, stream, a.key0, a.key1);
+                __builtin_amdgcn_s_setprio(2);
+                const float r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
+                __builtin_amdgcn_s_setprio(0);
+#pragma unroll
+                for (int q = 0; q < NQ; ++q) {
+                    const float zs[4] = {zz[q].a, zz[q].b, zz[q].c, zz[q].d};
+#pragma unroll
+                    for (int s = 0; s < 4; ++s)
+                        if (active && run) step(zs[s], r_mlp);
+                }
+            };
+            if (E == 16) {
+                pass(std::integral_constant<int, 4>{});
+            } else if (E == 8) {
+                pass(std::integral_constant<int, 2>{});
+            } else if (E == 4) {
+                pass(std::integral_constant<int, 1>{});
+            } else {
+                // E = 1: an evaluation before every step
                 F4 z{};
                 if (active && run) z = normals4(k >> 2, t, stream, a.key0, a.key1);
                 const float zs[4] = {z.a, z.b, z.c, z.d};
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    if (s > 0 && E == 1) r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
+                    const float r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
                     if (active && run) step(zs[s], r_mlp);
                 }
             }
