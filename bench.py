@@ -102,12 +102,18 @@ def parse():
     p.add_argument("--c5-total", type=int, default=1_000_000_000)
     p.add_argument("--c5-launches", type=int, default=7, help="launches the amplitudes are split over")
     p.add_argument("--c5-save", type=str, default="", help="write the per-amplitude result tables to this .npz")
+    p.add_argument("--c5-analyse", type=str, default="",
+                   help="only analyse result tables saved by --c5-save (CPU: the combination and the checks)")
     p.add_argument("--c5-learned", type=int, default=100_000_000,
                    help="runs of a learned proposal added to the combination (0: fixed amplitudes only)")
     p.add_argument("--c5-target", type=float, default=24.5, help="window centre N* of the learned proposal")
     p.add_argument("--c5-curriculum", type=str, default="17,18,19,20,21,22,23,24",
                    help="window centres the learned proposal is trained through before N*")
-    p.add_argument("--mlp-wg", type=int, default=2,
+    p.add_argument("--c5-stage-runs", type=int, default=20_000_000,
+                   help="runs of each curriculum stage's network from --c5-stage-from on (0: none)")
+    p.add_argument("--c5-stage-from", type=float, default=18.0,
+                   help="first curriculum centre whose network is run beside the final one")
+    p.add_argument("--mlp-wg", type=int, default=3,
                    help="256-lane workgroups per CU of the learned-bias sampler (waves per SIMD)")
     p.add_argument("--mlp-sampler", action="store_true",
                    help="time the learned-bias sampler alone (untrained network, r ~ 1) on the diffusion case")
@@ -230,10 +236,13 @@ def c5_run(args):
         print(f"[c5] amplitudes {[insts[i].A for i in g]}: {tm[0] / 1e3:.1f} s", file=sys.stderr, flush=True)
     wall = time.perf_counter() - t0
     steps = sum(r.total_steps for r in results)
+    for inst_, r in zip(insts, results):
+        r.amplitude = inst_.A
     learned = None
     if args.c5_learned > 0:
         learned = c5_learned_run(args, insts[0], results)
         results.append(learned.pop("result"))
+        results += learned.pop("stage_results")
     # lognormal estimates gated bin by bin (the drift-dominated regime of Sec. 2.4), the naive
     # estimate where a bin fails its gate; with 500 bins and 1e8 runs per amplitude a whole-result
     # gate fails by chance
@@ -241,35 +250,123 @@ def c5_run(args):
         np.savez_compressed(args.c5_save, **{f"counts_{i}": r.counts for i, r in enumerate(results)},
                             **{f"values_{i}": r.values for i, r in enumerate(results)},
                             edges=results[0].edges, amplitudes=np.array([i.A for i in insts]))
-    lp, el, nu = F.combine(results, 3)
-    ok = nu > 0
-    e = results[0].edges
-    good = ok & (el < 0.5 * math.log(10.0))          # bins known to better than half a decade
-    deepest = int(np.nonzero(good)[0].max()) if good.any() else -1
-    # the same with the no-extrapolation rule: lognormal bins need n_j >= exp(s^2 / 2)
-    lp_s, el_s, nu_s = F.combine(results, 3 + F.COMBINE_NO_EXTRAPOLATION)
-    good_s = (nu_s > 0) & (el_s < 0.5 * math.log(10.0))
-    deep_s = int(np.nonzero(good_s)[0].max()) if good_s.any() else -1
-    strict = {"combined_bins": int((nu_s > 0).sum()), "bins_within_half_decade": int(good_s.sum()),
-              "reach_log10_p": float(lp_s[deep_s] / math.log(10)) if deep_s >= 0 else None,
-              "reach_err_log10": float(el_s[deep_s] / math.log(10)) if deep_s >= 0 else None,
-              "reach_N": float(0.5 * (e[deep_s] + e[deep_s + 1])) if deep_s >= 0 else None,
-              "p_1e-40_N": (float(0.5 * (e[np.argmax((nu_s > 0) & (lp_s < -40 * math.log(10)))]
-                                        + e[np.argmax((nu_s > 0) & (lp_s < -40 * math.log(10))) + 1]))
-                            if np.any((nu_s > 0) & (lp_s < -40 * math.log(10))) else None)}
+    analysis = c5_analysis(results, n_fixed=len(insts))
     out = {"workload": "C5 bump potential, multi-bias A = 0..6" + (" + learned proposal" if learned else "") +
                        ", dN = 1e-4, 500 bins",
            "runs": sum(r.n_traj for r in results), "steps": steps, "wall_s": wall, "kernel_ms": kern_ms, "launches": len(groups),
            "traj_steps_per_s": steps / wall,
-           "gate_passed": [bool(r.lognormal_accepted()) for r in results],
-           "combined_bins": int(ok.sum()), "bins_within_half_decade": int(good.sum()),
-           "reach_log10_p": float(lp[deepest] / math.log(10)) if deepest >= 0 else None,
-           "reach_err_log10": float(el[deepest] / math.log(10)) if deepest >= 0 else None,
-           "reach_N": float(0.5 * (e[deepest] + e[deepest + 1])) if deepest >= 0 else None,
-           "no_extrapolation": strict}
+           "gate_passed": [bool(r.lognormal_accepted()) for r in results]}
+    out.update(analysis)
     if learned is not None:
         out["learned"] = learned
     print(json.dumps(out), flush=True)
+
+
+def c5_analysis(results, n_fixed):
+    """The large run's results combined bin by bin, and the checks of what the combination rests on.
+
+    - coverage and reach: estimator 3 (lognormal where a bin passes its gate, else the trusted
+      naive estimate) and the same with the no-extrapolation rule (a lognormal bin also needs
+      n_j >= exp(s_j^2/2)), over the fixed amplitudes alone and over every result;
+    - the learned proposals against each other: each one's naive estimates (n_j > 400 and
+      n_j > exp(s_j^2), no lognormal model) against the combination of the others, bin by bin,
+      with the z of the jackknife errors mapped through Student's t (15 degrees of freedom);
+    - the direct-sampling amplitudes' trusted naive estimates against the learned combination;
+    - each fixed amplitude's lognormal estimate minus the learned naive combination, in decades."""
+    import numpy as np
+    from scipy import stats
+    import paper_2206_11234_amd as F
+
+    L10 = math.log(10.0)
+    e = results[0].edges
+    B = len(e) - 1
+    centre = 0.5 * (e[1:] + e[:-1])
+
+    def spans(mask):
+        idx = np.nonzero(mask)[0]
+        out = []
+        for j in idx:
+            if out and j <= out[-1][1] + 2:
+                out[-1][1] = j
+            else:
+                out.append([j, j])
+        return [[round(float(e[a]), 3), round(float(e[b + 1]), 3)] for a, b in out]
+
+    def summary(res, est):
+        lp, el, nu = F.combine(res, est)
+        ok = nu > 0
+        good = ok & (el < 0.5 * L10)
+        deep = int(np.nonzero(good)[0].max()) if good.any() else -1
+        return {"combined_bins": int(ok.sum()), "bins_within_half_decade": int(good.sum()),
+                "reach_log10_p": float(lp[deep] / L10) if deep >= 0 else None,
+                "reach_err_log10": float(el[deep] / L10) if deep >= 0 else None,
+                "reach_N": float(centre[deep]) if deep >= 0 else None, "covered_N": spans(ok)}
+
+    def zstats(z):
+        z = np.asarray(z, np.float64)
+        if z.size == 0:
+            return None
+        zn = stats.norm.ppf(np.clip(stats.t.cdf(z, 15), 1e-300, 1.0 - 1e-16))
+        return {"comparisons": int(z.size), "beyond_3sigma": int(np.sum(np.abs(zn) > 3.0)),
+                "rms_z": float(np.sqrt(np.mean(zn ** 2))),
+                "chi2_p": float(stats.chi2.sf(float(np.sum(zn ** 2)), z.size))}
+
+    NX = F.COMBINE_NO_EXTRAPOLATION
+    out = {}
+    out.update(summary(results, 3))
+    out["no_extrapolation"] = summary(results, 3 + NX)
+    out["fixed_only"] = summary(results[:n_fixed], 3)
+    out["fixed_only_no_extrapolation"] = summary(results[:n_fixed], 3 + NX)
+    lp, el, nu = F.combine(results, 3)
+    below = np.nonzero((nu > 0) & (lp < -40 * L10))[0]
+    out["p_1e-40_N"] = float(centre[below[0]]) if below.size else None
+    learned = list(range(n_fixed, len(results)))
+    if len(learned) >= 2:
+        z = []
+        for i in learned:
+            lo, eo, no = F.combine([results[k] for k in learned if k != i], 0)
+            li, ei, ni = F.combine([results[i]], 0)
+            m = (ni > 0) & (no > 0)
+            z += list((li[m] - lo[m]) / np.hypot(ei[m], eo[m]))
+        out["learned_leave_one_out"] = zstats(z)
+    if learned:
+        ll, le, ln = F.combine([results[i] for i in learned], 0)
+        out["learned_naive_covered_N"] = spans(ln > 0)
+        direct, offsets = {}, {}
+        for i in range(n_fixed):
+            fl, fe, fn = F.combine([results[i]], 0)
+            m = (fn > 0) & (ln > 0)
+            st = zstats((fl[m] - ll[m]) / np.hypot(fe[m], le[m])) if m.any() else None
+            if st is not None:
+                direct[f"A{results[i].amplitude:g}"] = st
+            n = results[i].count[:B]
+            m = (n >= 400) & (ln > 0) & np.isfinite(results[i].log_p_ln[:B])
+            if m.any():
+                d = (results[i].log_p_ln[:B][m] - ll[m]) / L10
+                offsets[f"A{results[i].amplitude:g}"] = {"bins": int(m.sum()), "median": float(np.median(d)),
+                                                         "min": float(d.min()), "max": float(d.max()),
+                                                         "N": [round(float(centre[m].min()), 2), round(float(centre[m].max()), 2)]}
+        out["fixed_naive_vs_learned"] = direct
+        out["fixed_lognormal_minus_learned_decades"] = offsets
+    return out
+
+
+def c5_analyse_saved(path):
+    """--c5-analyse: the analysis of result tables written by --c5-save (no GPU needed)."""
+    import numpy as np
+    import paper_2206_11234_amd as F
+    from paper_2206_11234_amd import api
+
+    z = np.load(path)
+    edges = z["edges"]
+    n_res = len([k for k in z.files if k.startswith("counts_")])
+    lay = F.layout(len(edges) - 1, 16)
+    res = [api.Result(edges=edges, n_sub=16, counts=z[f"counts_{i}"], values=z[f"values_{i}"], lay=lay)
+           for i in range(n_res)]
+    amps = list(z["amplitudes"])
+    for i, r in enumerate(res):
+        r.amplitude = float(amps[i]) if i < len(amps) else float("nan")
+    print(json.dumps(c5_analysis(res, n_fixed=len(amps))), flush=True)
 
 
 def c5_learned_run(args, base, fixed_results):
@@ -296,6 +393,7 @@ def c5_learned_run(args, base, fixed_results):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     rounds = []
+    stage_thetas = []
     stages = [float(c) for c in args.c5_curriculum.split(",") if c] + [target]
     for si, centre in enumerate(stages):
         theta, _, rep = F.train_proposal(dataclasses.replace(inst0, target_N=centre), args.train_seed + 100 * si, theta,
@@ -307,17 +405,33 @@ def c5_learned_run(args, base, fixed_results):
             r["centre"] = centre
             print(f"[c5] train round: {json.dumps(r)}", file=sys.stderr, flush=True)
         rounds += rep
+        if si < len(stages) - 1:
+            stage_thetas.append((centre, theta.copy()))
     train_s = time.perf_counter() - t0
     inst = dataclasses.replace(inst0, mlp=dataclasses.replace(p0, values=theta))
     res, _, tm = F.run(inst, 0, block=256, wg_per_cu=args.mlp_wg, chunk=1, timing=True)
     print(f"[c5] learned: {tm[0] / 1e3:.1f} s", file=sys.stderr, flush=True)
+    # the curriculum's networks aimed between the fixed amplitudes' trusted reach and N*, each on
+    # a noise stream of its own: their ln w spreads little in their windows, so those bins pass the
+    # no-extrapolation rule of the combination
+    stage_results, stage_info = [], []
+    if args.c5_stage_runs > 0:
+        for k, (centre, th) in enumerate([c for c in stage_thetas if c[0] >= args.c5_stage_from]):
+            si = dataclasses.replace(inst0, name=f"C5_learned_{centre:g}", target_N=centre,
+                                     mlp=dataclasses.replace(p0, values=th), n_traj=args.c5_stage_runs,
+                                     stream=len(fixed_results) + 1 + k)
+            r, _, tms = F.run(si, 0, block=256, wg_per_cu=args.mlp_wg, chunk=1, timing=True)
+            stage_results.append(r)
+            stage_info.append({"centre": centre, "runs": r.n_traj, "steps": r.total_steps, "kernel_ms": tms[0]})
+            print(f"[c5] stage network {centre:g}: {tms[0] / 1e3:.1f} s", file=sys.stderr, flush=True)
     e = res.edges
     j = [i for i in range(len(e) - 1) if e[i] >= target - 0.3 and e[i + 1] <= target + 0.3]
 
     def ess_per_1e6(r):
         return float(np.nansum(np.exp(2 * r.lse_w[j] - r.lse_w2[j]))) / r.n_traj * 1e6
 
-    return {"result": res, "runs": res.n_traj, "steps": res.total_steps, "kernel_ms": tm[0], "train_s": train_s,
+    return {"result": res, "stage_results": stage_results, "stages": stage_info,
+            "runs": res.n_traj, "steps": res.total_steps, "kernel_ms": tm[0], "train_s": train_s,
             "window": [target - 0.3, target + 0.3], "window_bins": len(j),
             "window_runs": int(res.count[j].sum()), "ess_per_1e6_runs": ess_per_1e6(res),
             "fixed_ess_per_1e6_runs": {f"A{a.A:g}": ess_per_1e6(r) for a, r in zip(W.c5_multi(), fixed_results)},
@@ -433,8 +547,8 @@ def learned_gain(args):
     lj = learned["gpu_s_to_1pct_jk"]
     # measured, not extrapolated: the best fixed bias runs on (id-range shards of n_eval runs)
     # for args.fixed_budget_s GPU-seconds; the error it reaches is the target eps, and each
-    # learned proposal runs in shards of 2^17 runs (one per lane of the launch) until it reaches
-    # the same eps
+    # learned proposal runs in shards of one run per lane of its launch until it reaches the same
+    # eps (a shard lasts as long as its longest run, so this is a lower bound on the gain)
     measured = None
     if best is not None and args.fixed_budget_s > 0:
         A_best = float(best["label"].split("=")[1])
@@ -443,7 +557,8 @@ def learned_gain(args):
         eps_m = fx["median_rel_err_jk"]
         measured = {"eps": eps_m, "fixed": dict(fx, label=best["label"])}
         for label, params in (("learned", p1),) + ((("learned objective 0", p_obj0),) if obj0 else ()):
-            lm = run_until(F, dataclasses.replace(inst0, mlp=params), lo, hi, eps_m, 1 << 17, 60.0,
+            lanes = F.device_cus() * args.mlp_wg * 256
+            lm = run_until(F, dataclasses.replace(inst0, mlp=params), lo, hi, eps_m, lanes, 60.0,
                            block=256, wg_per_cu=args.mlp_wg, chunk=1)
             lm["gain"] = fx["gpu_s"] / lm["gpu_s"] if lm["reached"] else None
             measured[label] = lm
@@ -611,6 +726,9 @@ def main():
         return
     if args.learned:
         print(json.dumps(learned_gain(args)), flush=True)
+        return
+    if args.c5_analyse:
+        c5_analyse_saved(args.c5_analyse)
         return
     if args.c5:
         c5_run(args)

@@ -170,7 +170,18 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
     // learned proposal: this wave's share of the network's A operands
     MlpTiles tiles;
     if constexpr (BIAS == BIAS_MLP) mlp_load_tiles(a.mlp_params, tiles);
+    // the single-instance learned sampler reads its operand tiles from one LDS copy
+    constexpr bool TILES_LDS = BIAS == BIAS_MLP && SINGLE;
+    __shared__ bf16x8 tile_lds[TILES_LDS ? MLP_N_FRAG * 64 : 1];
+    if constexpr (TILES_LDS) {
+        if (threadIdx.x < 64) mlp_store_tiles_lds(tiles, tile_lds);
+        __syncthreads();
+    }
     MlpConsts mc{};
+    auto network = [&](float phi_, float N_) {
+        if constexpr (TILES_LDS) return mlp_forward_lds(tile_lds, mc, phi_, N_);
+        else return mlp_forward(tiles, mc, phi_, N_);
+    };
     int single_inst = 0;
     if constexpr (SINGLE) {
         // the one instance with runs (others in the batch, if any, have none)
@@ -285,7 +296,7 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) zz[q] = normals4((k >> 2) + q, t, stream, a.key0, a.key1);
                 __builtin_amdgcn_s_setprio(2);
-                const float r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
+                const float r_mlp = network(phi, static_cast<float>(k) * C.dN);
                 __builtin_amdgcn_s_setprio(0);
 #pragma unroll
                 for (int q = 0; q < NQ; ++q) {
@@ -308,7 +319,7 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
                 const float zs[4] = {z.a, z.b, z.c, z.d};
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    const float r_mlp = mlp_forward(tiles, mc, phi, static_cast<float>(k) * C.dN);
+                    const float r_mlp = network(phi, static_cast<float>(k) * C.dN);
                     if (active && run) step(zs[s], r_mlp);
                 }
             }
@@ -427,10 +438,11 @@ __global__ __launch_bounds__(256) void fpt_step_mlp_kernel(StepArgs a) {
     fpt_step_body<POT, BIAS_MLP, LDS>(a);
 }
 
-// One instance: uniform constants in scalar registers, fitted to two waves per SIMD so that one
-// wave's matrix-core work overlaps another's vector work.
+// One instance: uniform constants in scalar registers and the network's operand tiles in LDS,
+// fitted to three waves per SIMD so that one wave's matrix-core work and latency overlap the
+// others' vector work.
 template <int POT, bool LDS>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2, 2))) void fpt_step_mlp1_kernel(StepArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3, 3))) void fpt_step_mlp1_kernel(StepArgs a) {
     fpt_step_body<POT, BIAS_MLP, LDS, true>(a);
 }
 

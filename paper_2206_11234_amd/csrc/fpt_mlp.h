@@ -183,4 +183,76 @@ __device__ __forceinline__ float mlp_forward(const MlpTiles &T, const MlpConsts 
     return M.out_scale * o;
 }
 
+// The single-instance sampler keeps the operand tiles in LDS instead (17 fragments x 64 lanes x
+// 16 B = 17 KiB per workgroup, one copy shared by its waves, read at each use) and evaluates the
+// two N-blocks one after the other, so that its registers fit three waves per SIMD: the step
+// loop is latency-bound and the third wave hides more of it than the register tiles save.  The
+// matrix instructions and their operands are those of mlp_forward, so the result is the same bit
+// for bit.
+constexpr int MLP_N_FRAG = 17;
+constexpr size_t MLP_TILE_LDS_BYTES = static_cast<size_t>(MLP_N_FRAG) * 64 * sizeof(bf16x8);
+
+__device__ __forceinline__ void mlp_store_tiles_lds(const MlpTiles &T, bf16x8 *L) {
+    const int l = __lane_id();
+    L[0 * 64 + l] = T.a1[0];
+    L[1 * 64 + l] = T.a1[1];
+#pragma unroll
+    for (int mb = 0; mb < 2; ++mb)
+#pragma unroll
+        for (int kb = 0; kb < 5; ++kb) L[(2 + 5 * mb + kb) * 64 + l] = T.a2[mb][kb];
+#pragma unroll
+    for (int kb = 0; kb < 5; ++kb) L[(12 + kb) * 64 + l] = T.a3[kb];
+}
+
+__device__ __forceinline__ float mlp_forward_lds(const bf16x8 *L, const MlpConsts &M, float phi, float N) {
+    const int l = __lane_id();
+    const int h = l >> 5;
+    const __bf16 z = __builtin_bit_cast(__bf16, (uint16_t)0);
+    const float x0 = (phi - M.in_mean[0]) * M.in_inv[0];
+    const float x1 = (N - M.in_mean[1]) * M.in_inv[1];
+    const float x2 = (M.target_N - M.in_mean[2]) * M.in_inv[2];
+    bf16x8 xin;
+    xin[0] = (__bf16)x0;
+    xin[1] = (__bf16)x1;
+    xin[2] = (__bf16)x2;
+    xin[3] = (__bf16)1.0f;
+#pragma unroll
+    for (int s = 4; s < 8; ++s) xin[s] = z;
+    bf16x8 zero8;
+#pragma unroll
+    for (int s = 0; s < 8; ++s) zero8[s] = z;
+    const f32x16 zacc = {};
+    float out[2];
+#pragma unroll 1
+    for (int nb = 0; nb < 2; ++nb) {
+        // N-block nb: the trajectories of lanes 32 nb .. 32 nb + 31
+        const bf16x8 bx = (h == nb) ? xin : zero8;
+        f32x16 d0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L[0 * 64 + l], bx, zacc, 0, 0, 0);
+        f32x16 d1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L[1 * 64 + l], bx, zacc, 0, 0, 0);
+        bf16x8 b[5];
+        act_to_operands(d0, d1, b);
+        // keep each layer's LDS reads next to their use: hoisted together they would hold all
+        // 17 tiles in registers again
+        __builtin_amdgcn_sched_barrier(0);
+        d0 = zacc;
+        d1 = zacc;
+#pragma unroll
+        for (int kb = 0; kb < 5; ++kb) {
+            d0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L[(2 + kb) * 64 + l], b[kb], d0, 0, 0, 0);
+            d1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L[(7 + kb) * 64 + l], b[kb], d1, 0, 0, 0);
+        }
+        act_to_operands(d0, d1, b);
+        __builtin_amdgcn_sched_barrier(0);
+        f32x16 o = zacc;
+#pragma unroll
+        for (int kb = 0; kb < 5; ++kb) o = __builtin_amdgcn_mfma_f32_32x32x16_bf16(L[(12 + kb) * 64 + l], b[kb], o, 0, 0, 0);
+        out[nb] = o[0];
+    }
+    // row 0 lives in lanes 0-31: lane l < 32 has its own trajectory in N-block 0, lane l >= 32
+    // reads N-block 1's from lane l - 32
+    const float other = __shfl(out[1], l ^ 32, 64);
+    const float o = (h == 0) ? out[0] : other;
+    return M.out_scale * o;
+}
+
 }  // namespace fpt

@@ -480,12 +480,15 @@ WsMap ws_map(const Prepared &P, int n_wg) {
 void resolve_cfg(const Device &d, const Prepared &P, LaunchCfg &c, bool &lds) {
     const bool mlp = P.bias == PYFPT_BIAS_MLP;
     if (c.block <= 0) c.block = mlp ? 256 : 512;
-    // the learned bias with one active instance fits two waves per SIMD (two 256-thread
+    // the learned bias with one active instance fits three waves per SIMD (three 256-thread
     // workgroups per CU); otherwise one
-    if (c.wg_per_cu <= 0) c.wg_per_cu = mlp ? (P.order.size() == 1 ? 2 : 1) : 2;
+    const bool mlp1 = mlp && P.order.size() == 1;
+    if (c.wg_per_cu <= 0) c.wg_per_cu = mlp ? (mlp1 ? 3 : 1) : 2;
     if (c.chunk <= 0) c.chunk = 1;
-    // LDS budget per workgroup: the CU's LDS shared by its resident workgroups
-    const size_t budget = std::min<size_t>(d.max_lds, 160 * 1024 / static_cast<size_t>(c.wg_per_cu));
+    // LDS budget per workgroup: the CU's LDS shared by its resident workgroups, less the
+    // single-instance learned sampler's static copy of the network's operand tiles
+    const size_t share = std::min<size_t>(d.max_lds, 160 * 1024 / static_cast<size_t>(c.wg_per_cu));
+    const size_t budget = share - (mlp1 ? std::min(share, fpt::MLP_TILE_LDS_BYTES) : 0);
     lds = P.lay.slice_bytes <= budget;
 }
 
