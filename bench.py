@@ -238,10 +238,14 @@ def c5_run(args):
     steps = sum(r.total_steps for r in results)
     for inst_, r in zip(insts, results):
         r.amplitude = inst_.A
+        r.label = f"A{inst_.A:g}"
     learned = None
     if args.c5_learned > 0:
         learned = c5_learned_run(args, insts[0], results)
         results.append(learned.pop("result"))
+        results[-1].label = f"learned {args.c5_target:g}"
+        for st, r in zip(learned["stages"], learned["stage_results"]):
+            r.label = f"learned {st['centre']:g}"
         results += learned.pop("stage_results")
     # lognormal estimates gated bin by bin (the drift-dominated regime of Sec. 2.4), the naive
     # estimate where a bin fails its gate; with 500 bins and 1e8 runs per amplitude a whole-result
@@ -249,7 +253,8 @@ def c5_run(args):
     if args.c5_save:
         np.savez_compressed(args.c5_save, **{f"counts_{i}": r.counts for i, r in enumerate(results)},
                             **{f"values_{i}": r.values for i, r in enumerate(results)},
-                            edges=results[0].edges, amplitudes=np.array([i.A for i in insts]))
+                            edges=results[0].edges, amplitudes=np.array([i.A for i in insts]),
+                            labels=np.array([r.label for r in results]))
     analysis = c5_analysis(results, n_fixed=len(insts))
     out = {"workload": "C5 bump potential, multi-bias A = 0..6" + (" + learned proposal" if learned else "") +
                        ", dN = 1e-4, 500 bins",
@@ -348,6 +353,30 @@ def c5_analysis(results, n_fixed):
                                                          "N": [round(float(centre[m].min()), 2), round(float(centre[m].max()), 2)]}
         out["fixed_naive_vs_learned"] = direct
         out["fixed_lognormal_minus_learned_decades"] = offsets
+
+    def val(c, j):
+        lp_, el_, nu_ = c
+        return [round(float(lp_[j] / L10), 3), round(float(el_[j] / L10), 3)] if nu_[j] > 0 else None
+
+    # every 25th bin, combined: [log10 P, error in decades] or null where nothing contributes
+    combos = {"all": F.combine(results, 3), "all_no_extrapolation": F.combine(results, 3 + NX),
+              "fixed": F.combine(results[:n_fixed], 3), "fixed_no_extrapolation": F.combine(results[:n_fixed], 3 + NX)}
+    out["selected_bins"] = [dict(bin=j, N=round(float(centre[j]), 3), **{k: val(c, j) for k, c in combos.items()})
+                            for j in list(range(0, B, 25)) + [B - 1]]
+    # each result's own estimates where it has at least 400 runs, at a few bins of the far tail
+    rows = []
+    for Nq in (18.85, 19.97, 21.16, 22.42, 23.49, 24.04):
+        j = int(np.argmin(np.abs(centre - Nq)))
+        for i, r in enumerate(results):
+            n = int(r.count[j])
+            if n < 400:
+                continue
+            s2 = float(r.m2_lnw[j]) * n / (n - 1)
+            sd = math.sqrt(max(s2, 0.0))
+            rows.append({"N": round(float(centre[j]), 3), "result": getattr(r, "label", str(i)), "runs": n,
+                         "naive": round(float(r.log_p[j] / L10), 2), "lognormal": round(float(r.log_p_ln[j] / L10), 2),
+                         "s_lnw": round(sd, 2), "n_ge_exp_s2_half": bool(n >= math.exp(min(s2 / 2, 700.0)))})
+    out["per_result"] = rows
     return out
 
 
@@ -364,8 +393,10 @@ def c5_analyse_saved(path):
     res = [api.Result(edges=edges, n_sub=16, counts=z[f"counts_{i}"], values=z[f"values_{i}"], lay=lay)
            for i in range(n_res)]
     amps = list(z["amplitudes"])
+    labels = list(z["labels"]) if "labels" in z.files else []
     for i, r in enumerate(res):
         r.amplitude = float(amps[i]) if i < len(amps) else float("nan")
+        r.label = str(labels[i]) if i < len(labels) else (f"A{amps[i]:g}" if i < len(amps) else f"learned #{i - len(amps)}")
     print(json.dumps(c5_analysis(res, n_fixed=len(amps))), flush=True)
 
 
