@@ -578,8 +578,9 @@ def learned_gain(args):
     lj = learned["gpu_s_to_1pct_jk"]
     # measured, not extrapolated: the best fixed bias runs on (id-range shards of n_eval runs)
     # for args.fixed_budget_s GPU-seconds; the error it reaches is the target eps, and each
-    # learned proposal runs in shards of one run per lane of its launch until it reaches the same
-    # eps (a shard lasts as long as its longest run, so this is a lower bound on the gain)
+    # learned proposal runs in shards of one run per lane until it reaches the same eps.  A shard
+    # lasts as long as its longest run, so the learned side is latency-bound: it runs one wave per
+    # SIMD (each run gets the SIMD to itself), and the gain is still a lower bound
     measured = None
     if best is not None and args.fixed_budget_s > 0:
         A_best = float(best["label"].split("=")[1])
@@ -588,9 +589,9 @@ def learned_gain(args):
         eps_m = fx["median_rel_err_jk"]
         measured = {"eps": eps_m, "fixed": dict(fx, label=best["label"])}
         for label, params in (("learned", p1),) + ((("learned objective 0", p_obj0),) if obj0 else ()):
-            lanes = F.device_cus() * args.mlp_wg * 256
+            lanes = F.device_cus() * 256
             lm = run_until(F, dataclasses.replace(inst0, mlp=params), lo, hi, eps_m, lanes, 60.0,
-                           block=256, wg_per_cu=args.mlp_wg, chunk=1)
+                           block=256, wg_per_cu=1, chunk=1)
             lm["gain"] = fx["gpu_s"] / lm["gpu_s"] if lm["reached"] else None
             measured[label] = lm
             print(f"[learned] measured to eps {eps_m:.3f}: {label} {json.dumps(lm)}", file=sys.stderr, flush=True)

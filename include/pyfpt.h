@@ -90,7 +90,9 @@ typedef struct pyfpt_potential {
  *   W1[64][3], b1[64], W2[64][64], b2[64], w3[64], b3        (row-major, W[out][in]).
  * The network is evaluated on the matrix cores with binary32 accumulation and bfloat16
  * activations, every step (eval_every = 1) or once per group of 4, 8 or 16 steps at the
- * group's first step (eval_every = 4, 8 or 16; the bias is then held for the group). */
+ * group's first step (eval_every = 4, 8 or 16; the bias is then held for the group).  The
+ * sampler's tanh is accurate to the bfloat16 its result is rounded to (a clamped polynomial,
+ * within a third of a bfloat16 ulp of tanh); pyfpt_train_proposal's gradients use tanh. */
 typedef struct pyfpt_mlp {
     const void *params;              /* device pointer, 4481 bfloat16 */
     int32_t hidden;                  /* must be 64 */
