@@ -289,7 +289,7 @@ __device__ __forceinline__ void fpt_step_body(const StepArgs &a) {
             // vector work with the evaluation's matrix-core chains (they are the normals of
             // counters k/4 .. k/4 + E/4 - 1, the ones the steps would draw; a lane whose run ends
             // early leaves the rest unused).  The evaluation runs at a raised wave priority, so
-            // that it finishes sooner while the SIMD's other wave fills the gaps with steps.
+            // that it finishes sooner while the SIMD's other waves fill the gaps with steps.
             auto pass = [&](auto nq_tag) {
                 constexpr int NQ = decltype(nq_tag)::value;
                 F4 zz[NQ];
