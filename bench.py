@@ -490,7 +490,7 @@ def learned_gain(args):
     base = dataclasses.replace(W.c2(args.n_eval)[3], edges=edges)
     eps = 0.01
     out = {"workload": f"far-tail window ({lo:g}, {hi:g}] of the diffusion case, P ~ 1e-30", "fixed": [],
-           "n_eval": args.n_eval}
+           "n_eval": args.n_eval, "eval_every": args.eval_every}
 
     results = {}
 
@@ -662,6 +662,12 @@ def learned_summary(full):
                     "errors from the Kish ESS (gain_jackknife: the same with jackknife errors); "
                     "best fixed = lowest among the fixed amplitudes with > 400 window runs",
             "objective": "cross entropy (1), tempered",
+            # the learned sampler on its evaluation runs: fpt_step_mlp1_kernel's rate, and its matrix-core
+            # flop (34 MFMA 32x32x16 per 64 trajectories per evaluation) against the dense bf16 peak
+            "sampler": {"kernel": "fpt_step_mlp1_kernel", "kernel_ms": L["kernel_ms"],
+                        "traj_steps_per_s": L["steps_per_s"], "eval_every": full.get("eval_every"),
+                        "mfma_frac_bf16_peak": (L["steps_per_s"] * 34 * 32 * 32 * 16 * 2 / 64 / full["eval_every"]
+                                                / 2.5e15) if full.get("eval_every") else None},
             "objective_0": ({k: full["objective_0"][k] for k in ("ess", "median_rel_err", "median_rel_err_jk", "log10_p",
                                                                  "gpu_s_to_1pct", "train_s")}
                             if full.get("objective_0") else None),
