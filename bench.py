@@ -151,9 +151,11 @@ def cpu_model() -> str:
     return "unknown"
 
 
-def cpu_baseline(insts, target_s):
+def cpu_baseline(insts, target_s, gpu_steps=None):
     """The oracle (binary32 mirror, all host threads) on a bounded sample of the same runs, and
-    on one thread over the first runs of the same sample (a few seconds)."""
+    on one thread over the first runs of the same sample (a few seconds).  With gpu_steps (the
+    GPU pass's trajectory-steps per instance) the rate is weighted by the GPU's step mix: the
+    oracle's time for that pass is sum_i steps_i / rate_i, each instance at its own sampled rate."""
     import numpy as np
     import oracle as O
     to_model = O.Model.from_instance
@@ -164,6 +166,7 @@ def cpu_baseline(insts, target_s):
     threads = 0
     share = target_s / len(insts)
     sample = []
+    rates = []
     for inst in insts:
         n = 256
         while True:
@@ -176,6 +179,7 @@ def cpu_baseline(insts, target_s):
         elapsed += dt
         steps += int(tr.k.sum())
         threads = tr.threads
+        rates.append(int(tr.k.sum()) / dt)
         sample.append(f"{inst.name}:{n}")
     # one thread: the first ids of the first drift-dominated instance (about 3 s)
     one = insts[0]
@@ -188,7 +192,14 @@ def cpu_baseline(insts, target_s):
         if e1 >= 1.5 or n1 >= one.n_traj:
             break
         n1 = int(min(one.n_traj, n1 * min(8.0, max(2.0, 3.0 / max(e1, 1e-3)))))
-    return {"value": steps / elapsed, "unit": "traj-steps/s", "cores": threads, "kind": "oracle",
+    value = steps / elapsed
+    weighting = "time share: each instance sampled for about the same time"
+    if gpu_steps is not None and sum(gpu_steps) > 0:
+        value = sum(gpu_steps) / sum(g / r for g, r in zip(gpu_steps, rates))
+        weighting = "the GPU pass's step mix: sum of its steps over sum of steps_i / rate_i"
+    return {"value": value, "unit": "traj-steps/s", "cores": threads, "kind": "oracle",
+            "weighting": weighting, "rate_time_share": steps / elapsed,
+            "rate_per_instance": {inst.name: r for inst, r in zip(insts, rates)},
             "cpu_model": cpu_model(), "single_core": s1 / e1,
             "single_core_sample": f"{one.name}: first {n1} ids, {s1} steps in {e1:.2f} s on one thread",
             "sample": "first ids of each instance: " + ", ".join(sample) + f"; {steps} steps in {elapsed:.1f} s"}
@@ -857,7 +868,7 @@ def main():
     if not args.no_learned:
         out["learned_vs_fixed"] = learned_summary(learned_gain(args))
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(insts, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(insts, args.cpu_seconds, [r.total_steps for r in results])
     print(json.dumps(out), flush=True)
 
 
