@@ -156,7 +156,6 @@ def cpu_baseline(insts, target_s, gpu_steps=None):
     on one thread over the first runs of the same sample (a few seconds).  With gpu_steps (the
     GPU pass's trajectory-steps per instance) the rate is weighted by the GPU's step mix: the
     oracle's time for that pass is sum_i steps_i / rate_i, each instance at its own sampled rate."""
-    import numpy as np
     import oracle as O
     to_model = O.Model.from_instance
     # per instance, double the prefix of ids until one run of the oracle takes at least a third
